@@ -1,0 +1,76 @@
+"""Gates of one Trotter slice (oracle; test infrastructure only).
+
+Drive term per site: h = (u^x X + u^y Y) / 2 (Sec. III, Eq. 8 in the
+normalisation of the workloads, with the 1/2 on the drive).  A slice of
+length dt is split second-order as U = R Z R (Strang), where
+
+    R = exp(-i (dt/2) h)   on every site,
+    Z = exp(-i dt sum_b c_b Z_b Z_{b+1})   (all ZZ terms commute, so exact),
+
+the rightmost factor acting first.  The paper's Eq. 4 is the first-order
+product of the same three kinds of factor.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+I2 = np.eye(2, dtype=np.complex128)
+X = np.array([[0, 1], [1, 0]], dtype=np.complex128)
+Y = np.array([[0, -1j], [1j, 0]], dtype=np.complex128)
+Z = np.array([[1, 0], [0, -1]], dtype=np.complex128)
+ZVALS = np.array([1.0, -1.0])  # eigenvalue of Z on |0>, |1>
+
+
+def _f(a: float, r: float) -> float:
+    """sin(a r) / r, continuous at r = 0."""
+    return a * np.sinc(a * r / np.pi)
+
+
+def _g(a: float, r: float) -> float:
+    """f'(r) / r = (a r cos(a r) - sin(a r)) / r^3, by series near r = 0."""
+    x = a * r
+    if x < 0.1:
+        x2 = x * x
+        # sum_{n>=1} (-1)^n (2n)/(2n+1)! x^(2n-2)
+        return a ** 3 * (-1.0 / 3.0 + x2 / 30.0 - x2 * x2 / 840.0
+                         + x2 ** 3 / 45360.0 - x2 ** 4 / 3991680.0)
+    return (x * np.cos(x) - np.sin(x)) / r ** 3
+
+
+def half_rotation(ux: float, uy: float, dt: float) -> np.ndarray:
+    """R = exp(-i (dt/2) (ux X + uy Y)/2) = cos(a r) I - i sin(a r)/r (ux X + uy Y).
+
+    a = dt/4, r = sqrt(ux^2 + uy^2).
+    """
+    a = dt / 4.0
+    r = float(np.hypot(ux, uy))
+    return np.cos(a * r) * I2 - 1j * _f(a, r) * (ux * X + uy * Y)
+
+
+def half_rotation_derivs(ux: float, uy: float, dt: float):
+    """(dR/dux, dR/duy) of ``half_rotation`` in closed form."""
+    a = dt / 4.0
+    r = float(np.hypot(ux, uy))
+    f = _f(a, r)
+    g = _g(a, r)
+    n = ux * X + uy * Y
+    dx = -a * ux * f * I2 - 1j * (g * ux * n + f * X)
+    dy = -a * uy * f * I2 - 1j * (g * uy * n + f * Y)
+    return dx, dy
+
+
+def zz_phase(phi: float) -> np.ndarray:
+    """exp(-i phi Z x Z) as a 2x2 array over (s, s'): exp(-i phi z_s z_s')."""
+    return np.exp(-1j * phi * np.outer(ZVALS, ZVALS))
+
+
+def couplings(problem, k: int) -> np.ndarray:
+    """c[l, b] = zz_mask_b u^zz[l, b] + xt_mask_b J[k, b], shape (M, N-1)."""
+    return (problem.zz_mask[None, :] * problem.uzz
+            + problem.xt_mask[None, :] * problem.J[k][None, :])
+
+
+def slice_rotations(problem, l: int) -> np.ndarray:
+    """R[j] for slice l (0-based), shape (N, 2, 2)."""
+    return np.array([half_rotation(problem.ux[l, j], problem.uy[l, j],
+                                   problem.dt) for j in range(problem.N)])

@@ -1,0 +1,174 @@
+"""Ensemble fidelity and its exact adjoint gradient (oracle; test infrastructure only).
+
+Objective (Sec. II, Eq. 7, scored on R product-state inputs per noise sample):
+
+    F = 1/(K R) sum_{k,r} |O_kr|^2,      O_kr = <T_r | a_M^{(k,r)}>
+
+Adjoint (App. A, Eqs. A1-A2): with a_l the forward state after slice l and
+b_{l+1} the target propagated backward through slices M..l+1, every derivative
+of O is a matrix element <b_{l+1}| G |a_l> of a local operator G placed where
+the control enters.  For the second-order slice U_l = R_l Z_l R_l:
+
+  * left (outer) half rotation of slice l:   G = dR_{l,j} R_{l,j}^dagger   at site j
+  * right (inner) half rotation of slice l+1: G = R_{l+1,j}^dagger dR_{l+1,j} at site j
+  * ZZ control of slice l on bond b:
+        G = -i dt (R_{l,b} Z R_{l,b}^dagger) (x) (R_{l,b+1} Z R_{l,b+1}^dagger)
+
+(the paper's Eq. A2 shows the first-order form without the -i dt factor; the
+factor and the positions follow from differentiating the slice).  All matrix
+elements at one boundary come from one pass of left/right transfer
+environments.  dF = 1/(K R) sum 2 Re(conj(O_kr) dO_kr), with the final forward
+overlap O_kr for every boundary.
+"""
+from __future__ import annotations
+
+from typing import Optional
+
+import numpy as np
+
+from . import gates, tebd
+from .mps import MPS, overlap, product_state, right_canonicalize
+
+
+def environments(bra: MPS, ket: MPS):
+    """Left E[0..N] and right F[0..N] transfer environments of <bra|ket>."""
+    N = len(ket)
+    E = [None] * (N + 1)
+    F = [None] * (N + 1)
+    E[0] = np.ones((1, 1), np.complex128)
+    for j in range(N):
+        E[j + 1] = sum(bra[j][:, s, :].conj().T @ E[j] @ ket[j][:, s, :]
+                       for s in range(2))
+    F[N] = np.ones((1, 1), np.complex128)
+    for j in range(N - 1, -1, -1):
+        F[j] = sum(ket[j][:, s, :] @ F[j + 1] @ bra[j][:, s, :].conj().T
+                   for s in range(2))
+    return E, F
+
+
+def transitions(bra: MPS, ket: MPS, E, F) -> np.ndarray:
+    """rho[j, s, s'] = <bra| (|s><s'|)_j |ket>, shape (N, 2, 2)."""
+    N = len(ket)
+    rho = np.zeros((N, 2, 2), np.complex128)
+    for j in range(N):
+        for s in range(2):
+            for t in range(2):
+                rho[j, s, t] = np.trace(bra[j][:, s, :].conj().T @ E[j]
+                                        @ ket[j][:, t, :] @ F[j + 1])
+    return rho
+
+
+def two_site_element(bra: MPS, ket: MPS, E, F, b: int, G1: np.ndarray,
+                     G2: np.ndarray) -> complex:
+    """<bra| (G1)_b (G2)_{b+1} |ket>."""
+    val = 0.0 + 0.0j
+    for s1 in range(2):
+        for t1 in range(2):
+            if G1[s1, t1] == 0:
+                continue
+            W = bra[b][:, s1, :].conj().T @ E[b] @ ket[b][:, t1, :]
+            for s2 in range(2):
+                for t2 in range(2):
+                    if G2[s2, t2] == 0:
+                        continue
+                    val += G1[s1, t1] * G2[s2, t2] * np.trace(
+                        bra[b + 1][:, s2, :].conj().T @ W
+                        @ ket[b + 1][:, t2, :] @ F[b + 2])
+    return complex(val)
+
+
+def boundary_insertions(problem, bra: MPS, ket: MPS, l: int, dux, duy, duzz):
+    """Accumulate every dO contribution at boundary l (1-based, 0..M):
+    pair (b_{l+1}, a_l)."""
+    N, M, dt = problem.N, problem.M, problem.dt
+    E, F = environments(bra, ket)
+    rho = transitions(bra, ket, E, F)
+    if l >= 1:                                   # outer half of slice l
+        s = l - 1
+        for j in range(N):
+            R = gates.half_rotation(problem.ux[s, j], problem.uy[s, j], dt)
+            dx, dy = gates.half_rotation_derivs(problem.ux[s, j],
+                                                problem.uy[s, j], dt)
+            dux[s, j] += np.sum((dx @ R.conj().T) * rho[j])
+            duy[s, j] += np.sum((dy @ R.conj().T) * rho[j])
+        for b in range(N - 1):
+            if not problem.zz_mask[b]:
+                continue
+            R1 = gates.half_rotation(problem.ux[s, b], problem.uy[s, b], dt)
+            R2 = gates.half_rotation(problem.ux[s, b + 1], problem.uy[s, b + 1], dt)
+            W1 = R1 @ gates.Z @ R1.conj().T
+            W2 = R2 @ gates.Z @ R2.conj().T
+            duzz[s, b] += -1j * dt * two_site_element(bra, ket, E, F, b, W1, W2)
+    if l <= M - 1:                               # inner half of slice l+1
+        s = l
+        for j in range(N):
+            R = gates.half_rotation(problem.ux[s, j], problem.uy[s, j], dt)
+            dx, dy = gates.half_rotation_derivs(problem.ux[s, j],
+                                                problem.uy[s, j], dt)
+            dux[s, j] += np.sum((R.conj().T @ dx) * rho[j])
+            duy[s, j] += np.sum((R.conj().T @ dy) * rho[j])
+
+
+def trajectory(problem, k: int, r: int, chi: Optional[int] = None,
+               stats=None):
+    """O_kr and dO_kr/du for one trajectory.
+
+    Returns (O, dux (M,N), duy (M,N), duzz (M,N-1)), all complex.
+    """
+    N, M = problem.N, problem.M
+    a = tebd.evolve(problem, product_state(problem.inputs[r]), k,
+                    keep_all=True, chi=chi, stats=stats)
+    T = problem.targets[r]
+    O = overlap(T, a[M])
+    b = right_canonicalize(T)
+    dux = np.zeros((M, N), np.complex128)
+    duy = np.zeros((M, N), np.complex128)
+    duzz = np.zeros((M, N - 1), np.complex128)
+    for l in range(M, -1, -1):
+        boundary_insertions(problem, b, a[l], l, dux, duy, duzz)
+        if l >= 1:
+            b = tebd.backward_slice(problem, b, l - 1, k, chi, stats)
+    return O, dux, duy, duzz
+
+
+def fidelity_grad(problem, chi: Optional[int] = None, trajectories=None,
+                  details: bool = False):
+    """F and dF/du over the ensemble (or over the listed (k, r) trajectories).
+
+    Returns a dict with F, g_ux, g_uy, g_uzz (float64, control layout) and the
+    overlaps O[k, r]; with ``details`` also the per-trajectory dO arrays.
+    """
+    N, M = problem.N, problem.M
+    if trajectories is None:
+        trajectories = [(k, r) for k in range(problem.K) for r in range(problem.R)]
+    n = len(trajectories)
+    F = 0.0
+    gux = np.zeros((M, N))
+    guy = np.zeros((M, N))
+    guzz = np.zeros((M, N - 1))
+    O_all = {}
+    per = {}
+    for (k, r) in trajectories:
+        O, dux, duy, duzz = trajectory(problem, k, r, chi)
+        O_all[(k, r)] = O
+        F += abs(O) ** 2
+        gux += 2.0 * np.real(np.conj(O) * dux)
+        guy += 2.0 * np.real(np.conj(O) * duy)
+        guzz += 2.0 * np.real(np.conj(O) * duzz)
+        if details:
+            per[(k, r)] = (dux, duy, duzz)
+    out = dict(F=F / n, g_ux=gux / n, g_uy=guy / n, g_uzz=guzz / n,
+               overlaps=O_all)
+    if details:
+        out["dO"] = per
+    return out
+
+
+def final_states(problem, chi: Optional[int] = None):
+    """a_M for every trajectory t = k R + r (list of MPS)."""
+    out = []
+    for k in range(problem.K):
+        for r in range(problem.R):
+            out.append(tebd.evolve(problem, product_state(problem.inputs[r]),
+                                   k, chi=chi))
+    return out

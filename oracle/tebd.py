@@ -1,0 +1,139 @@
+"""TEBD with SVD truncation (oracle; test infrastructure only).
+
+One slice of the time grid (Sec. II, Eq. 4, taken second order):
+
+    a_l = R_l . trunc[ Z_l . (R_l a_{l-1}) ]
+
+R_l is the product of the single-site half rotations, Z_l the layer of ZZ
+phases.  Z_l is applied bond by bond in a sweep; after each bond the two-site
+tensor is split by an SVD and compressed to at most chi singular values (the
+compression to a maximum bond size after every step, Sec. II).  Every bond is
+split, also where its phase is zero, so the truncation is uniform.
+
+Canonical form: an MPS entering a left-to-right sweep has its orthogonality
+centre on site 0 and every other site right-isometric; the sweep leaves the
+centre on site N-1 (sites 0..N-2 left-isometric), and a right-to-left sweep
+mirrors this.  Slices alternate direction: forward slice l (1-based) sweeps
+left to right when l is odd; backward slice l sweeps left to right when M - l
+is even.
+
+Truncation rule: singular values sorted in descending order, keep
+    k = max(1, min(chi, #{i : sigma_i >= eps * sigma_1}))
+and, with renormalisation on, replace sigma_{1..k} by sigma_{1..k} / ||sigma_{1..k}||_2.
+"""
+from __future__ import annotations
+
+from typing import Dict, List, Optional
+
+import numpy as np
+
+from . import gates
+from .mps import MPS, copy
+
+
+def keep_count(S: np.ndarray, chi: int, eps: float) -> int:
+    if S.size == 0 or S[0] <= 0.0:
+        return 1
+    return max(1, min(int(chi), int(np.count_nonzero(S >= eps * S[0]))))
+
+
+def _svd(m: np.ndarray):
+    try:
+        return np.linalg.svd(m, full_matrices=False)
+    except np.linalg.LinAlgError:  # pragma: no cover - gesdd fallback
+        import scipy.linalg
+        return scipy.linalg.svd(m, full_matrices=False, lapack_driver="gesvd")
+
+
+def split_two_site(theta: np.ndarray, chi: int, eps: float, renormalize: bool,
+                   left_to_right: bool, stats: Optional[List[Dict]] = None):
+    """Split theta (Dl, 2, 2, Dr) into (Dl, 2, k) and (k, 2, Dr).
+
+    Left to right: left factor U (left-isometric), right factor diag(s) V^dagger
+    (new centre).  Right to left: left factor U diag(s), right V^dagger.
+    """
+    Dl, _, _, Dr = theta.shape
+    U, S, Vh = _svd(theta.reshape(Dl * 2, 2 * Dr))
+    k = keep_count(S, chi, eps)
+    k = min(k, S.size)
+    s = S[:k].copy()
+    tot = float(np.sum(S ** 2))
+    if stats is not None:
+        stats.append(dict(k=k, discarded=float(np.sum(S[k:] ** 2)) / tot if tot > 0 else 0.0,
+                          gap=float(S[k - 1] - S[k]) / S[0] if k < S.size else np.inf,
+                          sigma=S.copy()))
+    if renormalize:
+        s = s / np.linalg.norm(s)
+    if left_to_right:
+        left = U[:, :k]
+        right = s[:, None] * Vh[:k, :]
+    else:
+        left = U[:, :k] * s[None, :]
+        right = Vh[:k, :]
+    return left.reshape(Dl, 2, k), right.reshape(k, 2, Dr)
+
+
+def zz_layer(mps: MPS, phis: np.ndarray, left_to_right: bool, chi: int,
+             eps: float, renormalize: bool,
+             stats: Optional[List[Dict]] = None) -> MPS:
+    """Apply prod_b exp(-i phis[b] Z_b Z_{b+1}) by a truncated bond sweep."""
+    out = copy(mps)
+    N = len(out)
+    order = range(N - 1) if left_to_right else range(N - 2, -1, -1)
+    for b in order:
+        theta = np.einsum("asb,btc->astc", out[b], out[b + 1])
+        theta = theta * gates.zz_phase(phis[b])[None, :, :, None]
+        out[b], out[b + 1] = split_two_site(theta, chi, eps, renormalize,
+                                            left_to_right, stats)
+    return out
+
+
+def rotation_layer(mps: MPS, G: np.ndarray) -> MPS:
+    """A_j[:, s, :] <- sum_t G[j, s, t] A_j[:, t, :] on every site."""
+    return [np.einsum("st,atb->asb", G[j], A) for j, A in enumerate(mps)]
+
+
+def forward_slice(problem, mps: MPS, l: int, k: int, chi: Optional[int] = None,
+                  stats=None) -> MPS:
+    """a_l from a_{l-1}; ``l`` is 0-based (slice l+1 of the time grid)."""
+    chi = problem.chi if chi is None else chi
+    R = gates.slice_rotations(problem, l)
+    phis = problem.dt * gates.couplings(problem, k)[l]
+    ltr = (l + 1) % 2 == 1
+    a = rotation_layer(mps, R)
+    a = zz_layer(a, phis, ltr, chi, problem.eps, problem.renormalize, stats)
+    return rotation_layer(a, R)
+
+
+def backward_slice(problem, mps: MPS, l: int, k: int, chi: Optional[int] = None,
+                   stats=None) -> MPS:
+    """b_l = U_l^dagger b_{l+1} (with truncation); ``l`` is 0-based."""
+    chi = problem.chi if chi is None else chi
+    Rh = np.conj(np.transpose(gates.slice_rotations(problem, l), (0, 2, 1)))
+    phis = problem.dt * gates.couplings(problem, k)[l]
+    ltr = (problem.M - (l + 1)) % 2 == 0
+    b = rotation_layer(mps, Rh)
+    b = zz_layer(b, -phis, ltr, chi, problem.eps, problem.renormalize, stats)
+    return rotation_layer(b, Rh)
+
+
+def evolve(problem, mps: MPS, k: int, l_begin: int = 0,
+           l_end: Optional[int] = None, adjoint: bool = False,
+           chi: Optional[int] = None, keep_all: bool = False, stats=None):
+    """Apply slices l_begin..l_end-1 (0-based) forward, or, with ``adjoint``,
+    the adjoint slices l_end-1 down to l_begin.  Returns the final MPS, or the
+    list of all intermediate states when ``keep_all``."""
+    l_end = problem.M if l_end is None else l_end
+    states = [mps]
+    cur = mps
+    if not adjoint:
+        for l in range(l_begin, l_end):
+            cur = forward_slice(problem, cur, l, k, chi, stats)
+            if keep_all:
+                states.append(cur)
+    else:
+        for l in range(l_end - 1, l_begin - 1, -1):
+            cur = backward_slice(problem, cur, l, k, chi, stats)
+            if keep_all:
+                states.append(cur)
+    return states if keep_all else cur

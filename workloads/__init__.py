@@ -1,0 +1,241 @@
+"""Seeded synthetic workloads for ensemble-robust GRAPE on qubit-chain MPS.
+
+This module only draws random numbers and lays out arrays: piecewise-constant
+control amplitudes, crosstalk samples, product-state inputs and the target MPS
+tensors of the tasks in Secs. III-IV of the paper (parallel X, parallel CNOT,
+GHZ).  It holds none of the propagation, truncation, overlap or gradient
+arithmetic.  Both the CPU oracle and the HIP library consume what it returns,
+and neither side's code lives here.
+
+Conventions shared by every consumer
+------------------------------------
+* Sites j = 0..N-1 of an open chain, bond b couples (b, b+1).
+* Computational basis |0> <-> Z = +1.
+* A site tensor is a complex128 array of shape (D_l, 2, D_r).
+* Controls are float64: ``ux[l, j]``, ``uy[l, j]`` (shape (M, N)) and
+  ``uzz[l, b]`` (shape (M, N-1)); slice l = 0..M-1 here is slice l+1 of the
+  paper's 1-based time grid (Sec. II, Eq. 4).
+* ``zz_mask[b]`` marks bonds that carry the controllable coupling u^zz,
+  ``xt_mask[b]`` marks bonds that carry the static crosstalk J (Sec. III,
+  Eqs. 8-9, ZZ part only).
+* ``J[k, b]`` is the crosstalk strength of noise sample k on bond b, static in
+  time; trajectory t of a batch is (k, r) = (t // R, t % R).
+* Targets are returned right-canonical (every site right-isometric, the first
+  site carrying the norm, which is 1).
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import List, Optional
+
+import numpy as np
+
+__all__ = ["Problem", "CONFIGS", "make_problem", "haar_qubits"]
+
+
+@dataclasses.dataclass
+class Problem:
+    """A complete fidelity+gradient request: model, controls, ensemble, data."""
+
+    N: int
+    M: int
+    T: float
+    chi: int
+    eps: float
+    renormalize: bool
+    ux: np.ndarray          # (M, N) float64
+    uy: np.ndarray          # (M, N) float64
+    uzz: np.ndarray         # (M, N-1) float64
+    zz_mask: np.ndarray     # (N-1,) uint8
+    xt_mask: np.ndarray     # (N-1,) uint8
+    J: np.ndarray           # (K, N-1) float64, zero where xt_mask == 0
+    inputs: np.ndarray      # (R, N, 2) complex128 product-state qubits
+    targets: List[List[np.ndarray]]  # R target MPS, each N tensors (Dl,2,Dr)
+    task: str = "x"
+    name: str = ""
+
+    @property
+    def dt(self) -> float:
+        return self.T / self.M
+
+    @property
+    def K(self) -> int:
+        return int(self.J.shape[0])
+
+    @property
+    def R(self) -> int:
+        return int(self.inputs.shape[0])
+
+    @property
+    def n_traj(self) -> int:
+        return self.K * self.R
+
+    def subset(self, ks=None, rs=None) -> "Problem":
+        """Same controls, a sub-ensemble: noise samples ``ks``, inputs ``rs``."""
+        ks = list(range(self.K)) if ks is None else list(ks)
+        rs = list(range(self.R)) if rs is None else list(rs)
+        return dataclasses.replace(
+            self,
+            J=self.J[ks].copy(),
+            inputs=self.inputs[rs].copy(),
+            targets=[[a.copy() for a in self.targets[r]] for r in rs],
+        )
+
+
+# Workload shapes.  T for the gate tasks is 10 (units of 1/max drive); GHZ uses
+# T = N * tau_g / 8 with tau_g = 2 pi (coupling scale 1), the duration rule of
+# Sec. IV.
+CONFIGS = {
+    "xgate_n8": dict(task="x", N=8, M=50, T=10.0, chi=16, K=16, R=4,
+                     sigma=0.02, seed=0),
+    "xgate_n50": dict(task="x", N=50, M=100, T=10.0, chi=32, K=64, R=4,
+                      sigma=0.02, seed=1),
+    "cnot_n50": dict(task="cnot", N=50, M=200, T=10.0, chi=64, K=128, R=8,
+                     sigma=0.02, seed=2),
+    "ghz_n30": dict(task="ghz", N=30, M=300, T=30 * 2 * math.pi / 8, chi=128,
+                    K=256, R=1, sigma=0.05, seed=3),
+}
+
+
+def haar_qubits(rng: np.random.Generator, shape) -> np.ndarray:
+    """Independent Haar-random single-qubit states, normalised, shape (..., 2)."""
+    g = rng.standard_normal(tuple(shape) + (2, 2))
+    v = g[..., 0] + 1j * g[..., 1]
+    return v / np.linalg.norm(v, axis=-1, keepdims=True)
+
+
+def _masks(task: str, N: int):
+    b = np.arange(N - 1)
+    if task in ("x", "identity"):
+        return np.zeros(N - 1, np.uint8), np.ones(N - 1, np.uint8)
+    if task == "cnot":
+        # u^zz on the pair bonds (2p, 2p+1), crosstalk on the bonds between
+        # pairs (Sec. III, Eq. 11 with 0-based sites).
+        return (b % 2 == 0).astype(np.uint8), (b % 2 == 1).astype(np.uint8)
+    if task in ("ghz", "state"):
+        return np.ones(N - 1, np.uint8), np.ones(N - 1, np.uint8)
+    raise ValueError(f"unknown task {task!r}")
+
+
+def _product_mps(vecs: np.ndarray) -> List[np.ndarray]:
+    return [np.asarray(v, np.complex128).reshape(1, 2, 1).copy() for v in vecs]
+
+
+def _cnot_pair_mps(v0: np.ndarray, v1: np.ndarray) -> List[np.ndarray]:
+    """Right-canonical bond-2 MPS of CNOT(control 0, target 1) |v0>|v1>."""
+    psi = np.zeros((2, 2), np.complex128)
+    for s0 in range(2):
+        for s1 in range(2):
+            psi[s0, s1 ^ s0] = v0[s0] * v1[s1]
+    # psi = L @ Q with Q unitary: QR of psi^T gives psi = R^T Q^T.
+    q, r = np.linalg.qr(psi.T)
+    left = r.T            # (s0, beta)
+    right = q.T           # (beta, s1), orthonormal rows
+    return [left.reshape(1, 2, 2).copy(), right.reshape(2, 2, 1).copy()]
+
+
+def ghz_mps(N: int) -> List[np.ndarray]:
+    """The bond-2 GHZ MPS written out in Sec. IV (Eqs. 14-15).
+
+    The first site is a row vector, the last a column vector and the middle
+    sites are the projectors diag(1,0), diag(0,1); this form is already
+    right-canonical with unit norm.
+    """
+    h = 2.0 ** -0.5
+    first = np.zeros((1, 2, 2), np.complex128)
+    first[0, 0, 0] = h
+    first[0, 1, 1] = h
+    mid = np.zeros((2, 2, 2), np.complex128)
+    mid[0, 0, 0] = 1.0
+    mid[1, 1, 1] = 1.0
+    last = np.zeros((2, 2, 1), np.complex128)
+    last[0, 0, 0] = 1.0
+    last[1, 1, 0] = 1.0
+    return [first] + [mid.copy() for _ in range(N - 2)] + [last]
+
+
+def _targets(task: str, inputs: np.ndarray, N: int) -> List[List[np.ndarray]]:
+    out = []
+    for vecs in inputs:
+        if task == "x":
+            out.append(_product_mps(vecs[:, ::-1]))
+        elif task == "identity":
+            out.append(_product_mps(vecs))
+        elif task == "cnot":
+            mps: List[np.ndarray] = []
+            for p in range(N // 2):
+                mps += _cnot_pair_mps(vecs[2 * p], vecs[2 * p + 1])
+            if N % 2:
+                mps += _product_mps(vecs[-1:])
+            out.append(mps)
+        elif task == "ghz":
+            out.append(ghz_mps(N))
+        else:
+            raise ValueError(task)
+    return out
+
+
+def make_problem(name: Optional[str] = None, *, task: Optional[str] = None,
+                 N: Optional[int] = None, M: Optional[int] = None,
+                 T: Optional[float] = None, chi: Optional[int] = None,
+                 K: Optional[int] = None, R: Optional[int] = None,
+                 sigma: Optional[float] = None, seed: Optional[int] = None,
+                 eps: float = 1e-12, renormalize: bool = True,
+                 controls: str = "uniform", amp: float = 1.0,
+                 crosstalk: float = 1.0) -> Problem:
+    """Build a seeded synthetic problem.
+
+    ``name`` selects one of ``CONFIGS`` (keyword arguments override it).
+    ``controls``: ``"uniform"`` draws every amplitude from U(-amp, amp);
+    ``"pi_pulse"`` puts the global pi pulse u^x = pi/T on every site and adds
+    U(-amp, amp) to all amplitudes (a near-optimal X-gate pulse, so that F is
+    O(1) even at N = 50); ``"zero"`` sets every control to 0.
+    ``crosstalk`` scales the drawn J (0 disables the noise).
+    The seed is split with ``SeedSequence(seed).spawn(3)`` into the streams for
+    controls, crosstalk and inputs.
+    """
+    cfg = dict(CONFIGS[name]) if name is not None else dict(
+        task="x", N=8, M=50, T=10.0, chi=16, K=16, R=4, sigma=0.02, seed=0)
+    for key, val in dict(task=task, N=N, M=M, T=T, chi=chi, K=K, R=R,
+                         sigma=sigma, seed=seed).items():
+        if val is not None:
+            cfg[key] = val
+    task, N, M, T, chi, K, R, sigma, seed = (
+        cfg["task"], int(cfg["N"]), int(cfg["M"]), float(cfg["T"]),
+        int(cfg["chi"]), int(cfg["K"]), int(cfg["R"]), float(cfg["sigma"]),
+        int(cfg["seed"]))
+    if N < 2:
+        raise ValueError("N >= 2 required")
+    ss = np.random.SeedSequence(seed).spawn(3)
+    rc, rj, ri = (np.random.default_rng(s) for s in ss)
+    zz_mask, xt_mask = _masks(task, N)
+
+    if controls == "uniform":
+        ux = rc.uniform(-amp, amp, (M, N))
+        uy = rc.uniform(-amp, amp, (M, N))
+        uzz = rc.uniform(-amp, amp, (M, N - 1))
+    elif controls == "pi_pulse":
+        ux = math.pi / T + rc.uniform(-amp, amp, (M, N))
+        uy = rc.uniform(-amp, amp, (M, N))
+        uzz = rc.uniform(-amp, amp, (M, N - 1))
+    elif controls == "zero":
+        ux = np.zeros((M, N))
+        uy = np.zeros((M, N))
+        uzz = np.zeros((M, N - 1))
+    else:
+        raise ValueError(controls)
+    uzz = uzz * zz_mask[None, :]
+
+    J = rj.normal(0.0, sigma, (K, N - 1)) * crosstalk * xt_mask[None, :]
+
+    if task == "ghz":
+        inputs = np.zeros((R, N, 2), np.complex128)
+        inputs[..., 0] = 1.0
+    else:
+        inputs = haar_qubits(ri, (R, N))
+    targets = _targets(task, inputs, N)
+    return Problem(N=N, M=M, T=float(T), chi=int(chi), eps=float(eps),
+                   renormalize=bool(renormalize), ux=ux, uy=uy, uzz=uzz,
+                   zz_mask=zz_mask, xt_mask=xt_mask, J=J, inputs=inputs,
+                   targets=targets, task=task, name=name or task)
