@@ -1,0 +1,198 @@
+#!/usr/bin/env python3
+"""Throughput of batched ensemble fidelity+gradient evaluation on one MI355X.
+
+Workload: parallel CNOT on N = 50 qubits (25 pairs), chi = 64, M = 200 slices,
+K = 128 crosstalk samples x R = 8 random product inputs, complex128, seeded
+synthetic controls/crosstalk/inputs.  One step = one grape_fidelity_grad call:
+forward TEBD of all 1024 trajectories with checkpoints, the adjoint sweep with
+recomputation and the ensemble reduction, all in one persistent launch.
+
+Prints one JSON line (stdout); progress goes to stderr.
+"""
+import argparse
+import json
+import os
+import subprocess
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "noise-sample fidelity+grad evals/sec at N=50 chi=64 vs plain GPU; p50/p99 latency"
+FP64_PEAK_TFLOPS = 78.6   # MI355X fp64 vector (= fp64 matrix) peak
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def percentile(xs, q):
+    xs = sorted(xs)
+    if not xs:
+        return None
+    i = min(len(xs) - 1, max(0, int(round(q / 100.0 * (len(xs) - 1)))))
+    return xs[i]
+
+
+CPU_SCRIPT = r"""
+import os, sys, time, json
+sys.path.insert(0, {root!r})
+import workloads as W
+from oracle import grape
+p = W.make_problem({name!r})
+t0 = time.perf_counter()
+for r in range({n}):
+    grape.trajectory(p, 0, r)
+dt = time.perf_counter() - t0
+print(json.dumps(dict(seconds=dt)))
+"""
+
+
+def cpu_baseline(name, n_traj, R):
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    code = CPU_SCRIPT.format(root=ROOT, name=name, n=n_traj)
+    out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True,
+                         timeout=900)
+    if out.returncode != 0:
+        log(out.stderr)
+        return None
+    secs = json.loads(out.stdout.strip().splitlines()[-1])["seconds"]
+    samples = n_traj / R
+    return {"value": samples / secs, "unit": "noise-samples/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n_traj} of the {R} trajectories of noise sample k=0 (forward + adjoint "
+                      f"over all 200 slices), one process, 1 BLAS thread: {secs:.2f} s",
+            "seconds": secs}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="cnot_n50")
+    ap.add_argument("--cpu-sample", type=int, default=4,
+                    help="trajectories of the oracle timed on the host (0 disables)")
+    ap.add_argument("--plain", type=int, default=8,
+                    help="trajectories run one at a time for the plain GPU path (0 disables)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the trajectory batch "
+              "would be split across GPUs with one all-reduce of [F, grad], which this build "
+              "does not implement.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2603_03639_amd import build as B
+    if not os.path.exists(B.LIB_PATH):
+        B.build()
+    import paper_2603_03639_amd as P
+    import workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    p = W.make_problem(args.workload)
+    log(f"workload {args.workload}: N={p.N} M={p.M} chi={p.chi} K={p.K} R={p.R}")
+    f = lambda a: torch.as_tensor(np.ascontiguousarray(a, np.float64), device=dev)
+    ux, uy, uzz, J = f(p.ux), f(p.uy), f(p.uzz), f(p.J)
+    inputs = P.MPSBatch.from_product(p.inputs, device=dev)
+    tcap = max(max(A.shape[0] for A in T) for T in p.targets)
+    targets = P.MPSBatch.from_mps(p.targets, dcap=max(1, tcap), device=dev)
+    model = P.Model.from_problem(p)
+
+    # plan: grow the capacity bucket until no bond overflows (untimed)
+    t0 = time.perf_counter()
+    plan = P.grape_fidelity_grad(model, ux, uy, uzz, J, inputs, targets)
+    torch.cuda.synchronize()
+    log(f"plan: dcap={plan['dcap']} max_dim={plan['info']['max_dim']} "
+        f"({time.perf_counter() - t0:.2f} s incl. bucket search)")
+    call = P.GrapeCall(model, p.K, p.R, inputs, targets, plan["dcap"], device=dev)
+    stream = torch.cuda.current_stream()
+
+    for i in range(args.warmup):
+        call.run(ux, uy, uzz, J)
+        torch.cuda.synchronize()
+        log(f"warmup {i + 1}/{args.warmup} done")
+
+    lat = []
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for i in range(args.steps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        call.run(ux, uy, uzz, J)
+        e1.record(stream)
+        e1.synchronize()
+        lat.append(e0.elapsed_time(e1))
+        log(f"step {i + 1}/{args.steps}: {lat[-1]:.1f} ms")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    info = call.check()
+    ms = 1000.0 * wall / args.steps
+    value = p.K / (ms / 1000.0)
+    F = float(call.F.cpu())
+
+    flops = info["jacobi_flops"] + info["contraction_flops"]
+    kern_ms = sum(lat) / len(lat)
+    achieved = flops / (kern_ms / 1000.0) / 1e12
+    roofline = {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
+                "kernel": "k_grape", "flops_per_launch": flops,
+                "jacobi_flops_per_launch": info["jacobi_flops"],
+                "contraction_flops_per_launch": info["contraction_flops"],
+                "avg_launch_ms": kern_ms}
+
+    plain = None
+    if args.plain > 0:
+        n = min(args.plain, p.R)
+        sub_in = P.MPSBatch.from_product(p.inputs[:n], device=dev)
+        sub_tg = P.MPSBatch.from_mps(p.targets[:n], dcap=max(1, tcap), device=dev)
+        one_in = [P.MPSBatch(p.N, 1, 1, dev, sub_in.data[r:r + 1], sub_in.dims[r:r + 1])
+                  for r in range(n)]
+        one_tg = [P.MPSBatch(p.N, 1, sub_tg.dcap, dev, sub_tg.data[r:r + 1], sub_tg.dims[r:r + 1])
+                  for r in range(n)]
+        calls = [P.GrapeCall(model, 1, 1, one_in[r], one_tg[r], plan["dcap"], device=dev)
+                 for r in range(n)]
+        Jk = J[0:1].contiguous()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for r in range(n):
+            calls[r].run(ux, uy, uzz, Jk)
+            torch.cuda.synchronize()
+        secs = time.perf_counter() - t0
+        plain = {"value": (n / p.R) / secs, "unit": "noise-samples/s",
+                 "sample": f"{n} trajectories of noise sample k=0, one trajectory per launch",
+                 "seconds": secs}
+        log(f"plain one-trajectory-at-a-time path: {secs:.2f} s for {n} trajectories")
+
+    cpu = None
+    if args.cpu_sample > 0:
+        log("timing the CPU oracle ...")
+        cpu = cpu_baseline(args.workload, min(args.cpu_sample, p.R), p.R)
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "noise-samples/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"{args.workload}: parallel CNOT, N={p.N}, chi={p.chi}, M={p.M}, "
+                               f"K={p.K} noise samples x R={p.R} inputs, T={p.T}",
+                   "N": p.N, "chi": p.chi, "M": p.M, "K": p.K, "R": p.R,
+                   "dcap": plan["dcap"], "max_bond_dim": info["max_dim"]},
+        "trajectories_per_s": value * p.R,
+        "latency_ms": {"p50": percentile(lat, 50), "p99": percentile(lat, 99)},
+        "plain_gpu": plain,
+        "batched_vs_plain": (value / plain["value"]) if plain else None,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "fidelity": F,
+        "jacobi": {"svds": info["n_svd"], "total_sweeps": info["total_sweeps"],
+                   "max_sweeps": info["max_sweeps"]},
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,196 @@
+/*
+ * tnrg.h -- C ABI of the MI355X (gfx950) hot path of ensemble-robust GRAPE on
+ * qubit-chain matrix product states.
+ *
+ * The method (Le, Mintert, Ginossar, "Mitigating many-body quantum crosstalk
+ * with tensor-network robust control"):
+ *   - a chain of N qubits under H(t) = sum_j [u^x_j(t) X_j + u^y_j(t) Y_j]/2
+ *     + sum_b c_b(t) Z_b Z_{b+1}, with c_b = zz_mask_b u^zz_b(t)
+ *     + xt_mask_b J_b  (Sec. III, Eqs. 8-9, ZZ part of the crosstalk);
+ *   - piecewise-constant controls on M slices of length dt, each slice
+ *     applied as the second-order split U_l = R_l Z_l R_l with
+ *     R_l = exp(-i dt/2 sum_j h_j), Z_l = exp(-i dt sum_b c_b Z_b Z_{b+1})
+ *     (Sec. II, Eq. 4);
+ *   - the state is an MPS (Sec. II), the ZZ layer is applied by a bond sweep
+ *     with an SVD after every bond, compressed to at most chi singular values:
+ *     keep k = max(1, min(chi, #{sigma_i >= trunc_eps * sigma_1})) and, with
+ *     renormalize != 0, rescale the kept values to unit 2-norm;
+ *   - objective: F = 1/(K R) sum_{k,r} |<T_r|psi_kr(T)>|^2 over K crosstalk
+ *     samples and R input states (Sec. II, Eq. 7);
+ *   - gradient: the adjoint sweep of App. A (Eqs. A1-A2), with the exact
+ *     insertion operators of the second-order slice.
+ *
+ * Conventions
+ *   - Sites j = 0..N-1, bond b couples (b, b+1); |0> is the Z = +1 state.
+ *   - Slice index l = 0..M-1 (0-based).  Controls are row-major float64:
+ *     ux[l][j], uy[l][j] ([M][N]) and uzz[l][b] ([M][N-1]).
+ *   - Trajectory t of a K x R ensemble is (k, r) = (t / R, t % R).
+ *   - Complex numbers are tnrg_c128 {re, im} (the storage of complex128).
+ *   - <bra|ket> is conjugate-linear in bra.
+ *
+ * Ownership and errors
+ *   - The caller owns every buffer, including the workspace; the library
+ *     allocates no device memory, keeps no pointer past a call and keeps
+ *     only a per-process launch plan cache.
+ *   - Every compute call is asynchronous on the given HIP stream
+ *     (tnrg_stream is a hipStream_t; NULL is the default stream).
+ *   - Argument errors return a negative status at once and set the
+ *     thread-local message tnrg_last_error().  Device-side conditions (bond
+ *     capacity exceeded, Jacobi not converged, non-finite values) are written
+ *     as per-trajectory flags into the workspace; tnrg_status() synchronises
+ *     the stream and reads them.
+ *   - No C++ exception crosses this interface.
+ */
+#ifndef TNRG_H
+#define TNRG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+  double re, im;
+} tnrg_c128;
+
+typedef void *tnrg_stream; /* a hipStream_t */
+
+enum {
+  TNRG_OK = 0,
+  TNRG_EINVAL = -1,     /* bad argument */
+  TNRG_ENOMEM = -2,     /* workspace too small */
+  TNRG_EHIP = -3,       /* HIP runtime error */
+  TNRG_ENOCONV = -4,    /* Jacobi SVD hit max_sweeps (device flag) */
+  TNRG_ENONFINITE = -5, /* non-finite value met (device flag) */
+  TNRG_EOVERFLOW = -6,  /* a bond needed more than the capacity dcap */
+  TNRG_EUNSUPPORTED = -7
+};
+
+/* Device status flag bits (per trajectory, in the workspace). */
+enum {
+  TNRG_FLAG_OVERFLOW = 1,
+  TNRG_FLAG_NOCONV = 2,
+  TNRG_FLAG_NONFINITE = 4
+};
+
+/* Problem statement (Sec. II-III).  Host struct; the masks are host arrays. */
+typedef struct {
+  int32_t n;              /* qubits N, 2 <= N <= 256 */
+  int32_t m;              /* slices M >= 1 */
+  double dt;              /* slice length T / M */
+  int32_t chi;            /* maximum bond dimension (Sec. II, D_max) */
+  double trunc_eps;       /* relative singular-value cutoff, e.g. 1e-12 */
+  int32_t renormalize;    /* 1: rescale kept singular values to unit norm */
+  int32_t max_sweeps;     /* Jacobi sweep cap; 0 selects 40 */
+  const uint8_t *zz_mask; /* host [N-1]: bond carries the control u^zz */
+  const uint8_t *xt_mask; /* host [N-1]: bond carries the crosstalk J */
+} tnrg_model;
+
+/*
+ * A batch of MPS in device memory, one per trajectory, in a fixed-capacity
+ * layout.  Bond b (b = 0..N) has capacity cap_b = min(dcap, 2^b, 2^(N-b));
+ * site j stores a (D_j, 2, D_{j+1}) tensor inside a (cap_j, 2, cap_{j+1})
+ * row-major block: element (a, s, c) at
+ *     data[t * tnrg_mps_traj_elems(N, dcap) + tnrg_mps_site_offset(N, dcap, j)
+ *          + (a * 2 + s) * cap_{j+1} + c].
+ * bond_dim[t][b] = D_b with D_0 = D_N = 1.
+ */
+typedef struct {
+  int32_t n_traj;
+  int32_t n_sites;
+  int32_t dcap;
+  int32_t *bond_dim; /* device [n_traj][n_sites + 1] */
+  tnrg_c128 *data;   /* device [n_traj][tnrg_mps_traj_elems(n_sites, dcap)] */
+} tnrg_mps_batch;
+
+int32_t tnrg_bond_cap(int32_t n_sites, int32_t dcap, int32_t bond);
+int64_t tnrg_mps_site_offset(int32_t n_sites, int32_t dcap, int32_t site);
+int64_t tnrg_mps_traj_elems(int32_t n_sites, int32_t dcap);
+
+/*
+ * mps_evolve -- apply slices l_begin..l_end-1 of the time grid (Sec. II,
+ * Eq. 4, second order; TEBD with SVD truncation) to every MPS of psi, in
+ * place.  adjoint = 0: psi <- U_{l_end-1} ... U_{l_begin} psi, the ZZ sweep of
+ * slice l going left to right when l is even.  adjoint = 1:
+ * psi <- U_{l_begin}^dag ... U_{l_end-1}^dag psi, the sweep of slice l going
+ * left to right when M - 1 - l is even.  The MPS entering a left-to-right
+ * sweep must have its orthogonality centre on site 0 (sites 1..N-1
+ * right-isometric), and on site N-1 for a right-to-left sweep; product states
+ * qualify for both.
+ *   ux, uy, uzz: device controls [M][N], [M][N], [M][N-1].
+ *   J: device [psi->n_traj][N-1], the crosstalk of each trajectory.
+ *   ws: device workspace of at least mps_evolve_workspace_bytes() bytes.
+ */
+size_t mps_evolve_workspace_bytes(const tnrg_model *md, int32_t n_traj,
+                                  int32_t dcap);
+int mps_evolve(const tnrg_model *md, const double *ux, const double *uy,
+               const double *uzz, const double *J, int32_t l_begin,
+               int32_t l_end, int32_t adjoint, const tnrg_mps_batch *psi,
+               void *ws, size_t ws_bytes, tnrg_stream stream);
+
+/*
+ * mps_overlap -- out[t] = <bra_{t % bra->n_traj} | ket_t> by left transfer
+ * matrices (Sec. II, Eq. 7 overlap).  bra->n_traj must divide ket->n_traj.
+ * out is device [ket->n_traj].
+ */
+size_t mps_overlap_workspace_bytes(int32_t n_traj, int32_t n_sites,
+                                   int32_t dcap);
+int mps_overlap(const tnrg_mps_batch *bra, const tnrg_mps_batch *ket,
+                tnrg_c128 *out, void *ws, size_t ws_bytes, tnrg_stream stream);
+
+/*
+ * grape_fidelity_grad -- ensemble fidelity and its gradient with respect to
+ * every control amplitude (Sec. II, Eq. 7; App. A), for K crosstalk samples
+ * times R inputs, in one persistent launch with one workgroup per
+ * trajectory.  Forward states are checkpointed every ckpt_stride slices
+ * (0 selects ceil(sqrt(M))) and recomputed segment by segment during the
+ * adjoint sweep.
+ *   J: device [K][N-1].
+ *   inputs: R MPS (each canonical with centre on site 0; product states are).
+ *   targets: R MPS, right-canonical with unit norm (sites 1..N-1
+ *            right-isometric).
+ *   dcap: capacity of the internal states (bond dimensions above it raise
+ *         TNRG_FLAG_OVERFLOW); 0 selects min(chi, 2^(N/2)).
+ * Outputs (device): F[1]; g_ux[M][N], g_uy[M][N], g_uzz[M][N-1] (zero on
+ * bonds without u^zz); overlaps[K*R] (may be NULL); traj_dO (may be NULL):
+ * [K*R][2*M*N + M*(N-1)] complex dO/du per trajectory in the order ux, uy, uzz.
+ */
+size_t grape_workspace_bytes(const tnrg_model *md, int32_t K, int32_t R,
+                             int32_t dcap, int32_t ckpt_stride);
+int grape_fidelity_grad(const tnrg_model *md, const double *ux,
+                        const double *uy, const double *uzz, int32_t K,
+                        const double *J, int32_t R,
+                        const tnrg_mps_batch *inputs,
+                        const tnrg_mps_batch *targets, int32_t dcap,
+                        int32_t ckpt_stride, double *F, double *g_ux,
+                        double *g_uy, double *g_uzz, tnrg_c128 *overlaps,
+                        tnrg_c128 *traj_dO, void *ws, size_t ws_bytes,
+                        tnrg_stream stream);
+
+/*
+ * tnrg_status -- synchronise `stream`, then read the per-trajectory device
+ * flags that the last call on `ws` left (n_traj entries).  Copies them to
+ * host_flags when non-NULL; returns TNRG_OK, or the error of the most
+ * severe flag (OVERFLOW before NOCONV before NONFINITE).  stats (may be NULL)
+ * receives 6 counts over all trajectories: {max bond dimension reached, max
+ * Jacobi sweeps of one SVD, total Jacobi sweeps, number of SVDs, Jacobi flops
+ * (36 m n(n-1)/2 per sweep of an m x n matrix), contraction flops (two-site
+ * products, projections and transfer environments, 8 per complex
+ * multiply-add)}.
+ */
+int tnrg_status(const void *ws, int32_t n_traj, int32_t *host_flags,
+                int64_t *stats, tnrg_stream stream);
+
+/* Thread-local description of the last non-OK return. */
+const char *tnrg_last_error(void);
+
+/* Library version string. */
+const char *tnrg_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TNRG_H */

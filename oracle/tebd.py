@@ -59,8 +59,12 @@ def split_two_site(theta: np.ndarray, chi: int, eps: float, renormalize: bool,
     s = S[:k].copy()
     tot = float(np.sum(S ** 2))
     if stats is not None:
+        # the cut is decided by chi (not by the cutoff) when more singular
+        # values pass the cutoff than chi allows; only then can a near-tie
+        # sigma_k ~ sigma_{k+1} make the truncated state non-unique.
+        chi_cut = k < S.size and S[k] >= eps * S[0]
         stats.append(dict(k=k, discarded=float(np.sum(S[k:] ** 2)) / tot if tot > 0 else 0.0,
-                          gap=float(S[k - 1] - S[k]) / S[0] if k < S.size else np.inf,
+                          gap=float(S[k - 1] - S[k]) / S[0] if chi_cut else np.inf,
                           sigma=S.copy()))
     if renormalize:
         s = s / np.linalg.norm(s)
