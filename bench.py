@@ -73,6 +73,8 @@ def main():
     ap.add_argument("--workload", default="cnot_n50")
     ap.add_argument("--cpu-sample", type=int, default=4,
                     help="trajectories of the oracle timed on the host (0 disables)")
+    ap.add_argument("--profile", action="store_true",
+                    help="one extra call with in-kernel phase timers")
     ap.add_argument("--plain", type=int, default=8,
                     help="trajectories run one at a time for the plain GPU path (0 disables)")
     args = ap.parse_args()
@@ -108,6 +110,9 @@ def main():
     torch.cuda.synchronize()
     log(f"plan: dcap={plan['dcap']} max_dim={plan['info']['max_dim']} "
         f"({time.perf_counter() - t0:.2f} s incl. bucket search)")
+    from paper_2603_03639_amd import tune
+    tuned = tune.autotune(model, ux, uy, uzz, J, inputs, targets, plan["dcap"])
+    log(f"autotune: {tuned}")
     call = P.GrapeCall(model, p.K, p.R, inputs, targets, plan["dcap"], device=dev)
     stream = torch.cuda.current_stream()
 
@@ -145,6 +150,27 @@ def main():
                 "contraction_flops_per_launch": info["contraction_flops"],
                 "avg_launch_ms": kern_ms}
 
+    phases = None
+    if args.profile:
+        import dataclasses
+        mprof = dataclasses.replace(model, profile=True)
+        pc = P.GrapeCall(mprof, p.K, p.R, inputs, targets, plan["dcap"], device=dev)
+        pc.run(ux, uy, uzz, J)
+        pinfo = pc.check()
+        ticks = pinfo["phase_ticks"]
+        tot = max(ticks["total"], 1)
+        phases = {k: v / tot for k, v in ticks.items() if k != "total"}
+        phases["per_workgroup_total_s"] = tot / P.tnrg.CLOCK_HZ / (p.K * p.R)
+        ns = 1e9 / P.tnrg.CLOCK_HZ
+        phases["ns_per_jacobi_round"] = ticks["jacobi"] * ns / max(pinfo["jacobi_rounds"], 1)
+        phases["ns_per_lq_step"] = ticks["lq"] * ns / max(pinfo["lq_steps"], 1)
+        phases["ns_per_svd"] = (ticks["theta"] + ticks["lq"] + ticks["jacobi"] + ticks["finish"]) * ns / max(pinfo["n_svd"], 1)
+        phases["rounds_per_svd"] = pinfo["jacobi_rounds"] / max(pinfo["n_svd"], 1)
+        phases["lq_steps_per_svd"] = pinfo["lq_steps"] / max(pinfo["n_svd"], 1)
+        log("phase fractions of the persistent kernel: " +
+            ", ".join(f"{k} {v:.3f}" for k, v in phases.items()))
+        del pc
+
     plain = None
     if args.plain > 0:
         n = min(args.plain, p.R)
@@ -180,7 +206,9 @@ def main():
         "config": {"workload": f"{args.workload}: parallel CNOT, N={p.N}, chi={p.chi}, M={p.M}, "
                                f"K={p.K} noise samples x R={p.R} inputs, T={p.T}",
                    "N": p.N, "chi": p.chi, "M": p.M, "K": p.K, "R": p.R,
-                   "dcap": plan["dcap"], "max_bond_dim": info["max_dim"]},
+                   "dcap": plan["dcap"], "max_bond_dim": info["max_dim"],
+                   "threads_per_trajectory": tune.threads(plan["dcap"])},
+        "autotune": tuned,
         "trajectories_per_s": value * p.R,
         "latency_ms": {"p50": percentile(lat, 50), "p99": percentile(lat, 99)},
         "plain_gpu": plain,
@@ -188,6 +216,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "fidelity": F,
+        "phases": phases,
         "jacobi": {"svds": info["n_svd"], "total_sweeps": info["total_sweeps"],
                    "max_sweeps": info["max_sweeps"]},
     }

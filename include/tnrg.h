@@ -84,6 +84,7 @@ typedef struct {
   double trunc_eps;       /* relative singular-value cutoff, e.g. 1e-12 */
   int32_t renormalize;    /* 1: rescale kept singular values to unit norm */
   int32_t max_sweeps;     /* Jacobi sweep cap; 0 selects 40 */
+  int32_t profile;        /* 1: record per-phase clock ticks (tnrg_status) */
   const uint8_t *zz_mask; /* host [N-1]: bond carries the control u^zz */
   const uint8_t *xt_mask; /* host [N-1]: bond carries the crosstalk J */
 } tnrg_model;
@@ -152,7 +153,8 @@ int mps_overlap(const tnrg_mps_batch *bra, const tnrg_mps_batch *ket,
  *   targets: R MPS, right-canonical with unit norm (sites 1..N-1
  *            right-isometric).
  *   dcap: capacity of the internal states (bond dimensions above it raise
- *         TNRG_FLAG_OVERFLOW); 0 selects min(chi, 2^(N/2)).
+ *         TNRG_FLAG_OVERFLOW); 0 selects min(chi, 2^(N/2)); at most 32
+ *         (TNRG_EUNSUPPORTED above).
  * Outputs (device): F[1]; g_ux[M][N], g_uy[M][N], g_uzz[M][N-1] (zero on
  * bonds without u^zz); overlaps[K*R] (may be NULL); traj_dO (may be NULL):
  * [K*R][2*M*N + M*(N-1)] complex dO/du per trajectory in the order ux, uy, uzz.
@@ -174,14 +176,28 @@ int grape_fidelity_grad(const tnrg_model *md, const double *ux,
  * flags that the last call on `ws` left (n_traj entries).  Copies them to
  * host_flags when non-NULL; returns TNRG_OK, or the error of the most
  * severe flag (OVERFLOW before NOCONV before NONFINITE).  stats (may be NULL)
- * receives 6 counts over all trajectories: {max bond dimension reached, max
+ * receives 16 counts over all trajectories: {max bond dimension reached, max
  * Jacobi sweeps of one SVD, total Jacobi sweeps, number of SVDs, Jacobi flops
  * (36 m n(n-1)/2 per sweep of an m x n matrix), contraction flops (two-site
  * products, projections and transfer environments, 8 per complex
- * multiply-add)}.
+ * multiply-add)}, then, when the model's profile flag was set, clock ticks
+ * of a 100 MHz counter summed over workgroups for the phases {site load,
+ * theta, LQ preconditioner, Jacobi, split finish, left environments, right
+ * environments and insertions, whole kernel}, then {Jacobi rounds, LQ
+ * preconditioner steps}.
  */
 int tnrg_status(const void *ws, int32_t n_traj, int32_t *host_flags,
                 int64_t *stats, tnrg_stream stream);
+
+/*
+ * Launch plan (process-wide): the workgroup size used for internal states of
+ * capacity dcap, one of 64, 128 or 256 threads (1, 2 or 4 waves per
+ * trajectory); 0 restores the built-in choice.  Results do not depend on it
+ * beyond rounding.  The autotuner of the Python binding times the choices on
+ * the caller's workload and stores the fastest here.
+ */
+int tnrg_plan_set_threads(int32_t dcap, int32_t threads);
+int32_t tnrg_plan_threads(int32_t dcap);
 
 /* Thread-local description of the last non-OK return. */
 const char *tnrg_last_error(void);

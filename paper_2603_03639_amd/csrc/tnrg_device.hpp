@@ -16,14 +16,32 @@
 
 namespace tnrg {
 
-typedef double2 c2;
+// Complex double as a clang vector of two doubles (x = real, y = imaginary):
+// a builtin type, usable in every address space, 16-byte aligned like the
+// {re, im} storage of complex128.
+typedef double c2 __attribute__((ext_vector_type(2)));
+
+// LDS-qualified types: pointers into workgroup memory compile to ds_read /
+// ds_write instead of flat accesses.
+#define TNRG_LDS __attribute__((address_space(3)))
+typedef TNRG_LDS c2 sc2;
+typedef TNRG_LDS double sdbl;
+typedef TNRG_LDS int sint;
+typedef TNRG_LDS long long sll;
 
 constexpr int kMaxSites = 256;
+constexpr int kStats = 16;
+enum { kPhLoad = 8, kPhTheta, kPhLQ, kPhJacobi, kPhFinish, kPhEnvL, kPhEnvR, kPhTotal };
 constexpr int kMaxWaves = 16;
 
 // ----------------------------------------------------------------------------
-// complex helpers (double2: x = real, y = imaginary)
-__device__ __forceinline__ c2 cmk(double r, double i) { return make_double2(r, i); }
+// complex helpers (x = real, y = imaginary)
+__device__ __forceinline__ c2 cmk(double r, double i) {
+  c2 v;
+  v.x = r;
+  v.y = i;
+  return v;
+}
 __device__ __forceinline__ c2 cadd(c2 a, c2 b) { return cmk(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ c2 csub(c2 a, c2 b) { return cmk(a.x - b.x, a.y - b.y); }
 __device__ __forceinline__ c2 cconj(c2 a) { return cmk(a.x, -a.y); }
@@ -64,6 +82,13 @@ __device__ __forceinline__ M22 m22_dag(const M22& a) {
   r.m[2] = cconj(a.m[1]); r.m[3] = cconj(a.m[3]);
   return r;
 }
+// Row s of G applied to (x0, x1): G[s][0] x0 + G[s][1] x1, with selects
+// instead of a dynamically indexed register array.
+__device__ __forceinline__ c2 m22_row(const M22& G, int s, c2 x0, c2 x1) {
+  const c2 g0 = s ? G.m[2] : G.m[0];
+  const c2 g1 = s ? G.m[3] : G.m[1];
+  return cfma(g1, x1, cmul(g0, x0));
+}
 __device__ __forceinline__ M22 m22_mul(const M22& a, const M22& b) {
   M22 r;
   r.m[0] = cadd(cmul(a.m[0], b.m[0]), cmul(a.m[1], b.m[2]));
@@ -82,11 +107,21 @@ struct ModelDev {
   double eps;
   int renorm;
   int max_sweeps;
+  int profile;      // 1: accumulate phase clock ticks into the stats
   uint64_t zzm[4];  // bit b: bond b carries u^zz
   uint64_t xtm[4];  // bit b: bond b carries crosstalk J
 };
 __device__ __forceinline__ bool bit(const uint64_t* m, int b) {
-  return (m[b >> 6] >> (b & 63)) & 1ull;
+  // every word is read and the choice is made on values, never on an
+  // address, so the mask words (and the context holding them) stay in
+  // registers
+  const uint64_t w0 = m[0], w1 = m[1], w2 = m[2], w3 = m[3];
+  const int k = b >> 6;
+  uint64_t w = w0;
+  w = k == 1 ? w1 : w;
+  w = k == 2 ? w2 : w;
+  w = k == 3 ? w3 : w;
+  return (w >> (b & 63)) & 1ull;
 }
 
 // Capacity of bond b: min(dcap, 2^b, 2^(N-b)).
@@ -98,6 +133,14 @@ __host__ __device__ __forceinline__ int bond_cap(int N, int dcap, int b) {
   return c;
 }
 
+// Elements of the Jacobi working matrix for capacity cap: P2 (P2 + 1) with
+// P2 = pow2(2 cap) (padded columns plus one element of bank skew).
+__host__ __device__ inline long long x_elems(int cap) {
+  long long p = 1;
+  while (p < 2LL * cap) p <<= 1;
+  return p * (p + 1);
+}
+
 // Fixed-capacity MPS layout, built in LDS at kernel start.
 struct Layout {
   int N;
@@ -105,7 +148,8 @@ struct Layout {
   int cap[kMaxSites + 1];
   long long off[kMaxSites + 1];  // off[N] = elements per trajectory
 };
-__device__ void layout_build(Layout& L, int N, int dcap) {
+typedef TNRG_LDS Layout sLayout;
+__device__ __forceinline__ void layout_build(sLayout& L, int N, int dcap) {
   if (threadIdx.x == 0) {
     L.N = N;
     L.dcap = dcap;
@@ -125,38 +169,60 @@ __host__ __device__ inline long long site_offset_slow(int N, int dcap, int j) {
   return o;
 }
 
-// Per-workgroup context.  LDS buffers are sized from the capacity `cap`:
-//   LC, LO : 2 cap^2 complex  (centre tensor, other tensor / isometry Q)
-//   X      : 2 cap (2 cap + 1) complex (Jacobi working matrix)
-//   sig    : 2 cap doubles, perm : 2 cap ints
+// Per-workgroup context.  LDS buffers are sized from P2 = pow2(2 cap):
+//   LC, LO : P2^2 / 2 complex each (centre tensor, other tensor / isometry Q;
+//            together the LQ working matrix)
+//   X      : P2 (P2 + 1) complex (Jacobi working matrix)
+//   sig    : P2 doubles, perm : P2 ints
 struct Ctx {
   int tid, nt;
   int cap;
-  c2* LC;
-  c2* LO;
-  c2* X;
-  double* sig;
-  int* perm;
-  c2* X0;       // global scratch (2 cap (2 cap + 1)), the unrotated theta
-  Layout* L;    // layout of the internal states
-  int* sdims;   // LDS [kMaxSites + 1]
+  sc2* LC;
+  sc2* LO;
+  sc2* X;
+  sdbl* sig;
+  sint* perm;
+  c2* X0;       // global scratch (P2 (P2 + 1)), the unrotated theta
+  sLayout* L;   // layout of the internal states
+  sint* sdims;  // LDS [kMaxSites + 1]
   ModelDev md;
   // per-trajectory bookkeeping in LDS (written by thread 0)
-  int* sflag;
-  // [8]: max dim, max sweeps, total sweeps, svd count, Jacobi flops,
-  // contraction flops (theta, projection, environments), unused x2
-  long long* sstat;
-  double* red;       // LDS [kMaxWaves * 8]
-  int* sk;           // LDS scalar: kept singular values of the last split
-  double* sinv;      // LDS scalar: 1 / norm of kept singular values
+  sint* sflag;
+  // [kStats]: max dim, max sweeps, total sweeps, svd count, Jacobi flops,
+  // contraction flops (theta, projection, environments), Jacobi rounds, LQ
+  // steps, then phase
+  // clock ticks: site load/store, theta, LQ, Jacobi, split finish, left
+  // environments, right environments + insertions, whole kernel.
+  sll* sstat;
+  sdbl* red;       // LDS [kMaxWaves * 8]
+  sint* sk;          // LDS scalar: kept singular values of the last split
+  sdbl* sinv;        // LDS scalar: 1 / norm of kept singular values
+  sdbl* sd;          // LDS scratch scalars [4]
+  sint* si;          // LDS scratch scalars [4]
 };
+
+__device__ __forceinline__ void flag_or(Ctx& C, int v) {
+  __hip_atomic_fetch_or(C.sflag, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Phase timer (thread 0, constant-rate wall clock), active when md.profile.
+__device__ __forceinline__ long long ph_now(const Ctx& C) {
+  return (C.md.profile && C.tid == 0) ? (long long)wall_clock64() : 0;
+}
+__device__ __forceinline__ void ph_add(Ctx& C, int slot, long long& t0) {
+  if (C.md.profile && C.tid == 0) {
+    const long long t1 = (long long)wall_clock64();
+    C.sstat[slot] += t1 - t0;
+    t0 = t1;
+  }
+}
 
 // ----------------------------------------------------------------------------
 // Block-wide deterministic reduction of V complex values (V <= 4).  Every
 // thread passes its partial sums; the result is returned to every thread.
 // The summation order is fixed (butterfly inside each wave, waves in order).
 template <int V>
-__device__ void block_sum(Ctx& C, c2 (&v)[V]) {
+__device__ __forceinline__ void block_sum(Ctx& C, c2 (&v)[V]) {
   for (int o = 1; o < 64; o <<= 1) {
 #pragma unroll
     for (int i = 0; i < V; ++i) {
@@ -186,148 +252,463 @@ __device__ void block_sum(Ctx& C, c2 (&v)[V]) {
 }
 
 // ----------------------------------------------------------------------------
-// One-sided (Hestenes) Jacobi SVD of the len x nc matrix X held column-major
-// in LDS (column c at X + c*ldx).  Columns are rotated pairwise until every
-// pair is orthogonal to tol = len * 2^-52 relative to the column norms; the
-// columns then hold sigma_i u_i.  Pairs are visited in the round-robin
-// (circle) order, all disjoint pairs of a round in parallel; each pair's rows
-// are split over LPP lanes whose partial dot products are combined by a
-// butterfly, so every lane of the pair derives the same rotation.
-// Writes sig[c] = ||X_c||; returns the number of sweeps.
-__device__ int jacobi_lds(Ctx& C, c2* X, int len, int nc, int ldx) {
-  const int tid = C.tid, NT = C.nt;
-  const int P = (nc + 1) >> 1;
-  const int np = 2 * P, m = np - 1;
-  int LPP = 1;
-  while (LPP < 16 && P * LPP * 2 <= NT) LPP <<= 1;
-  const int slots = NT / LPP;
-  const int p_local = tid / LPP, q = tid % LPP;
-  const double tol = (double)len * 2.220446049250313e-16;
-  int sweeps = 0;
-  const int max_sweeps = C.md.max_sweeps;
-  for (int sw = 0; sw < max_sweeps; ++sw) {
-    int rotated = 0;
-    for (int r = 0; r < m; ++r) {
-      for (int pbase = 0; pbase < P; pbase += slots) {
-        const int pp = pbase + p_local;
-        int ci = 0, cj = 0;
-        bool valid = (p_local < slots) && (pp < P);
-        if (valid) {
-          if (pp == 0) {
-            ci = 0;
-            cj = 1 + (r % m);
-          } else {
-            ci = 1 + (r + pp) % m;
-            cj = 1 + (r - pp + m) % m;
-          }
-          valid = (ci < nc) && (cj < nc);
-        }
-        double a = 0.0, b = 0.0, gr = 0.0, gi = 0.0;
-        if (valid) {
-          const c2* xc = X + ci * ldx;
-          const c2* yc = X + cj * ldx;
-          for (int row = q; row < len; row += LPP) {
-            c2 x = xc[row], y = yc[row];
-            a = fma(x.x, x.x, fma(x.y, x.y, a));
-            b = fma(y.x, y.x, fma(y.y, y.y, b));
-            gr = fma(x.x, y.x, fma(x.y, y.y, gr));
-            gi = fma(x.x, y.y, fma(-x.y, y.x, gi));
-          }
-        }
-        for (int o = 1; o < LPP; o <<= 1) {
-          a += __shfl_xor(a, o, 64);
-          b += __shfl_xor(b, o, 64);
-          gr += __shfl_xor(gr, o, 64);
-          gi += __shfl_xor(gi, o, 64);
-        }
-        if (valid && a > 0.0 && b > 0.0) {
-          const double ag = sqrt(fma(gr, gr, gi * gi));
-          if (ag > tol * sqrt(a * b)) {
-            rotated = 1;
-            const double zeta = (b - a) / (2.0 * ag);
-            double t;
-            if (fabs(zeta) > 1e100)
-              t = 0.5 / zeta;
-            else
-              t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(fma(zeta, zeta, 1.0)));
-            const double cs = 1.0 / sqrt(fma(t, t, 1.0));
-            const double sn = cs * t;
-            const double er = gr / ag, ei = gi / ag;  // e = gamma / |gamma|
-            // x' = c x - s conj(e) y,  y' = s e x + c y
-            const double pr = sn * er, pi = sn * ei;  // s e
-            c2* xc = X + ci * ldx;
-            c2* yc = X + cj * ldx;
-            for (int row = q; row < len; row += LPP) {
-              c2 x = xc[row], y = yc[row];
-              c2 xn, yn;
-              // conj(s e) y = (pr - i pi)(y.x + i y.y)
-              xn.x = cs * x.x - (pr * y.x + pi * y.y);
-              xn.y = cs * x.y - (pr * y.y - pi * y.x);
-              // (s e) x = (pr + i pi)(x.x + i x.y)
-              yn.x = cs * y.x + (pr * x.x - pi * x.y);
-              yn.y = cs * y.y + (pr * x.y + pi * x.x);
-              xc[row] = xn;
-              yc[row] = yn;
-            }
-          }
-        } else if (valid && !(a == a && b == b)) {
-          // non-finite column: record and stop rotating this pair
-          atomicOr(C.sflag, 4);
-        }
-      }
-      __syncthreads();
-    }
-    ++sweeps;
-    if (tid == 0) C.sstat[4] += 18LL * len * nc * (nc - 1);
-    if (!__syncthreads_or(rotated)) break;
-    if (sw + 1 == max_sweeps && tid == 0) atomicOr(C.sflag, 2);
-  }
-  for (int c = tid; c < nc; c += NT) {
-    const c2* xc = X + c * ldx;
-    double s = 0.0;
-    for (int row = 0; row < len; ++row) s += cabs2(xc[row]);
-    C.sig[c] = sqrt(s);
-  }
-  __syncthreads();
-  return sweeps;
+// Butterfly sums over aligned groups of G lanes (G = 1, 2, 4, 8, 16) with DPP
+// lane permutations.  Every step combines a lane with the partner of an
+// involution (row mirror, half-row mirror, xor 1, xor 2) as a + b on one side
+// and b + a on the other, so all G lanes end with bit-identical sums.
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, true);
+  return __hiloint2double(hi, lo);
+}
+constexpr int kDppXor1 = 0xB1;        // quad_perm [1,0,3,2]
+constexpr int kDppXor2 = 0x4E;        // quad_perm [2,3,0,1]
+constexpr int kDppHalfMirror = 0x141; // lane i <-> 7-i within 8
+constexpr int kDppMirror = 0x140;     // lane i <-> 15-i within 16
+
+__device__ __forceinline__ double group_sum(double v, int G) {
+  if (G >= 16) v += dpp_d<kDppMirror>(v);
+  if (G >= 8) v += dpp_d<kDppHalfMirror>(v);
+  if (G >= 2) v += dpp_d<kDppXor1>(v);
+  if (G >= 4) v += dpp_d<kDppXor2>(v);
+  return v;
 }
 
-// Sort singular values (descending, ties by column index), choose the kept
-// count k by the truncation rule and compute 1/||sigma_{1..k}||.
-__device__ void choose_k(Ctx& C, int nc, int len, int capk) {
-  for (int c = C.tid; c < nc; c += C.nt) {
-    double v = C.sig[c];
+// Reciprocal square root and reciprocal from the hardware estimate refined by
+// one Newton step (the estimate's relative error is squared away), so the
+// rotation parameters cost two short dependent chains instead of the IEEE
+// sqrt/divide sequences.
+__device__ __forceinline__ double rsqrt_nr(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  const double e = fma(-x * y, y, 1.0);
+  return fma(0.5 * y, e, y);
+}
+__device__ __forceinline__ double rcp_nr(double x) {
+  const double y = __builtin_amdgcn_rcp(x);
+  const double e = fma(-x, y, 1.0);
+  return fma(y, e, y);
+}
+
+// Lanes per group so that n groups fit in NT lanes, at most 16.
+__device__ __forceinline__ int lanes_per(int n, int NT) {
+  int g = 1;
+  while (g < 16 && n * g * 2 <= NT) g <<= 1;
+  return g;
+}
+
+// Wave-uniform helpers built on DPP row operations and readlane.
+__device__ __forceinline__ double readlane_d(double v, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+  return __hiloint2double(hi, lo);
+}
+template <int CTRL>
+__device__ __forceinline__ unsigned long long dpp_u64(unsigned long long v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(v & 0xffffffffu), CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(v >> 32), CTRL, 0xF, 0xF, true);
+  return ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo;
+}
+__device__ __forceinline__ unsigned long long umax64(unsigned long long a, unsigned long long b) {
+  return a > b ? a : b;
+}
+// Max over the 64 lanes of a wave (all lanes active); wave-uniform result.
+__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long k) {
+  k = umax64(k, dpp_u64<kDppMirror>(k));
+  k = umax64(k, dpp_u64<kDppHalfMirror>(k));
+  k = umax64(k, dpp_u64<kDppXor1>(k));
+  k = umax64(k, dpp_u64<kDppXor2>(k));
+  unsigned long long m = 0;
+  for (int r = 0; r < 4; ++r) {
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(k & 0xffffffffu), 16 * r);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(k >> 32), 16 * r);
+    m = umax64(m, ((unsigned long long)hi << 32) | lo);
+  }
+  return m;
+}
+// Sum over the 64 lanes of a wave in a fixed order; wave-uniform result.
+__device__ __forceinline__ double wave_sum(double v) {
+  v = group_sum(v, 16);
+  return ((readlane_d(v, 0) + readlane_d(v, 16)) + readlane_d(v, 32)) + readlane_d(v, 48);
+}
+// Argmax key of a non-negative value at index c < 64: larger values win,
+// ties (to 2^-46 relative) go to the smaller index.
+__device__ __forceinline__ unsigned long long argmax_key(double v, int c) {
+  if (!(v >= 0.0)) return 0ull;
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  return (b & ~63ull) | (unsigned long long)(63 - c);
+}
+
+// ----------------------------------------------------------------------------
+// Row blocks.  A column of n rows is padded with zero rows to a power of two
+// `pad` and split over G lanes, lane q owning the contiguous rows
+// q*RPL .. q*RPL+RPL-1 (RPL = pad / G, a compile-time constant of the inner
+// loops, so they are straight-line code with immediate LDS offsets).
+__device__ __forceinline__ int pow2_at_least(int n) {
+  int p = 1;
+  while (p < n) p <<= 1;
+  return p;
+}
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// ----------------------------------------------------------------------------
+// Pivoted Householder LQ (QR with column pivoting of X^dag) as the
+// preconditioner of the one-sided Jacobi SVD.  Z (column-major, column r at
+// Z + r*ldz, ldz = pad(nz) rows with zero padding) holds X^dag: column r of Z
+// is the conjugated row r of X.  On return the lower-trapezoidal
+// L = P R^dag (len x rank, len = mz) with X = L Q^dag, Q orthonormal, is
+// written column-major into X (ldx, rows padded with zeros to pad(mz)); L has
+// the singular values and left singular vectors of X.  Columns of Z whose
+// remaining norm falls to thr2 = (len eps)^2 ||X||_F^2 stop the factorisation
+// (numerical rank).  Returns the rank (>= 1).  mz <= 64.
+// Scratch: nrm = C.sig (remaining squared norms by logical column), pcol =
+// C.perm (logical -> physical column of Z).
+template <int RQ>
+__device__ __forceinline__ void lq_apply(Ctx& C, sc2* Z, int ldz, int j, int mz, int G, const sc2* zp, c2 v0,
+                         double coef, sdbl* nrm, const sint* pcol) {
+  const int tid = C.tid, NT = C.nt;
+  const int grp = tid / G, q = tid % G;
+  const int ngrp = NT / G;
+  const int r0 = q * RQ;
+  // v_i = 0 (i < j), v0 (i = j), zp_i (i > j)
+  c2 v[RQ];
+#pragma unroll
+  for (int i = 0; i < RQ; ++i) {
+    const int row = r0 + i;
+    const c2 z = zp[row];
+    v[i] = row < j ? cmk(0.0, 0.0) : (row == j ? v0 : z);
+  }
+  for (int cc = grp; cc < mz - j - 1; cc += ngrp) {
+    sc2* zc = Z + pcol[j + 1 + cc] * ldz + r0;
+    c2 z[RQ];
+#pragma unroll
+    for (int i = 0; i < RQ; ++i) z[i] = zc[i];
+    c2 w = cmk(0.0, 0.0);
+#pragma unroll
+    for (int i = 0; i < RQ; ++i) w = cfmac(v[i], z[i], w);
+    w.x = group_sum(w.x, G);
+    w.y = group_sum(w.y, G);
+    const c2 cw = cscale(w, coef);
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < RQ; ++i) {
+      z[i] = csub(z[i], cmul(v[i], cw));
+      zc[i] = z[i];
+      if (r0 + i > j) s += cabs2(z[i]);
+    }
+    s = group_sum(s, G);
+    if (q == 0) nrm[j + 1 + cc] = s;
+  }
+}
+
+__device__ __forceinline__ int lq_pivot(Ctx& C, sc2* Z, int nz, int mz, int ldz, sc2* X, int ldx, double* thr2_out) {
+  sdbl* sh_d = C.sd;
+  sint* sh_i = C.si;
+  const int tid = C.tid, NT = C.nt;
+  sdbl* nrm = C.sig;
+  sint* pcol = C.perm;
+  const int padz = ldz;
+  const int G = uniform(max(min(lanes_per(mz, NT), padz), padz / 8));
+  const int RQ = uniform(padz / G);
+  {
+    const int grp = tid / G, q = tid % G;
+    for (int c = grp; c < mz; c += NT / G) {
+      double s = 0.0;
+      for (int i = 0; i < RQ; ++i) s += cabs2(Z[c * ldz + q * RQ + i]);
+      s = group_sum(s, G);
+      if (q == 0) {
+        nrm[c] = s;
+        pcol[c] = c;
+      }
+    }
+  }
+  __syncthreads();
+  if (tid < 64) {
+    const double f2 = wave_sum(tid < mz ? nrm[tid] : 0.0);
+    if (tid == 0) {
+      const double lt = (double)mz * 2.220446049250313e-16;
+      sh_d[3] = lt * lt * f2;
+    }
+  }
+  __syncthreads();
+  const double thr2 = sh_d[3];
+  *thr2_out = thr2;
+  const int steps = nz < mz ? nz : mz;
+  int rank = steps;
+  for (int j = 0; j < steps; ++j) {
+    if (tid < 64) {
+      const unsigned long long key =
+          wave_max_u64((tid >= j && tid < mz) ? argmax_key(nrm[tid], tid) : 0ull);
+      const int best = 63 - (int)(key & 63ull);
+      const double bv = nrm[best];
+      if (tid == 0) {
+        const int stop = !(key != 0ull && bv > thr2);
+        if (!stop) {
+          const int t = pcol[j];
+          pcol[j] = pcol[best];
+          pcol[best] = t;
+          nrm[best] = nrm[j];
+          nrm[j] = bv;
+          sc2* zj = Z + pcol[j] * ldz;
+          const c2 x0 = zj[j];
+          const double xn = bv * rsqrt_nr(bv);
+          const double a2 = cabs2(x0);
+          const double rax = a2 > 0.0 ? rsqrt_nr(a2) : 0.0;
+          const double ax0 = a2 * rax;
+          const c2 ph = a2 > 0.0 ? cscale(x0, rax) : cmk(1.0, 0.0);
+          // v = x + ph ||x|| e_j,  H x = -ph ||x|| e_j,  H = I - coef v v^dag
+          sh_d[0] = x0.x + ph.x * xn;
+          sh_d[1] = x0.y + ph.y * xn;
+          sh_d[2] = rcp_nr(xn * (xn + ax0));
+          zj[j] = cmk(-ph.x * xn, -ph.y * xn);
+        }
+        sh_i[0] = stop;
+      }
+    }
+    __syncthreads();
+    if (sh_i[0]) {
+      rank = j;
+      break;
+    }
+    if (tid == 0) C.sstat[7] += 1;  // LQ steps
+    const c2 v0 = cmk(sh_d[0], sh_d[1]);
+    const double coef = sh_d[2];
+    const sc2* zp = Z + pcol[j] * ldz;
+    switch (RQ) {
+      case 1: lq_apply<1>(C, Z, ldz, j, mz, G, zp, v0, coef, nrm, pcol); break;
+      case 2: lq_apply<2>(C, Z, ldz, j, mz, G, zp, v0, coef, nrm, pcol); break;
+      case 4: lq_apply<4>(C, Z, ldz, j, mz, G, zp, v0, coef, nrm, pcol); break;
+      default: lq_apply<8>(C, Z, ldz, j, mz, G, zp, v0, coef, nrm, pcol); break;
+    }
+    __syncthreads();
+  }
+  if (rank < 1) rank = 1;  // a zero matrix still yields one (zero) column
+  // L[pcol[c]][i] = conj(R[i][c]) = conj(Z[pcol[c]][i]) for i <= c, 0 below;
+  // padding rows mz .. pad-1 of every column are zero.
+  const int padx = pow2_at_least(mz);
+  for (int idx = tid; idx < rank * padx; idx += NT) {
+    const int i = idx / padx, c = idx - i * padx;
+    c2 val = cmk(0.0, 0.0);
+    int row = c;
+    if (c < mz) {
+      row = pcol[c];
+      if (i <= c) val = cconj(Z[row * ldz + i]);
+    }
+    X[i * ldx + row] = val;
+  }
+  __syncthreads();
+  return rank;
+}
+
+// ----------------------------------------------------------------------------
+// One-sided (Hestenes) Jacobi SVD of the len x ncol matrix X held column-major
+// in LDS (column c at X + c*ldx, rows padded with zeros to pad = pow2(len)).
+// Columns are rotated pairwise until every pair is orthogonal to len * 2^-52
+// relative to the column norms; the columns then hold sigma_i u_i.  Pairs
+// are visited in the round-robin (circle) order, all disjoint pairs of a
+// round in parallel; each pair's rows are split over G lanes whose partial
+// dot products are combined by a DPP butterfly, so every lane of the pair
+// derives the same rotation.  Columns whose squared norm is at most thr2
+// (rounding level of the whole matrix) take no part in rotations; after each
+// sweep they are dropped and the live columns are packed to the front, in
+// order.  Returns the number of live columns (>= 1); sig[c] holds ||X_c|| for
+// those.  *sweeps_out receives the number of sweeps.
+template <int RPL>
+__device__ __forceinline__ int jacobi_sweep(Ctx& C, sc2* X, int ldx, int n, int G, double thr2, double tol2) {
+  const int tid = C.tid;
+  const int P = (n + 1) >> 1;
+  const int m = 2 * P - 1;
+  const int pp = tid / G, q = tid % G;
+  const int r0 = q * RPL;
+  int ia = (pp == 0) ? 0 : 1 + pp;
+  int ib = (pp == 0) ? 1 : 1 + m - pp;
+  const bool slot_ok = pp < P;
+  int rotated = 0;
+  for (int r = 0; r < m; ++r) {
+    const bool valid = slot_ok && ia < n && ib < n;
+    sc2* xc = X + (valid ? ia : 0) * ldx + r0;
+    sc2* yc = X + (valid ? ib : 0) * ldx + r0;
+    c2 x[RPL], y[RPL];
+#pragma unroll
+    for (int i = 0; i < RPL; ++i) {
+      x[i] = xc[i];
+      y[i] = yc[i];
+    }
+    double a = 0.0, b = 0.0, gr = 0.0, gi = 0.0;
+#pragma unroll
+    for (int i = 0; i < RPL; ++i) {
+      a = fma(x[i].x, x[i].x, fma(x[i].y, x[i].y, a));
+      b = fma(y[i].x, y[i].x, fma(y[i].y, y[i].y, b));
+      gr = fma(x[i].x, y[i].x, fma(x[i].y, y[i].y, gr));
+      gi = fma(x[i].x, y[i].y, fma(-x[i].y, y[i].x, gi));
+    }
+    a = group_sum(a, G);
+    b = group_sum(b, G);
+    gr = group_sum(gr, G);
+    gi = group_sum(gi, G);
+    const double g2 = fma(gr, gr, gi * gi);
+    if (valid && a > thr2 && b > thr2 && g2 > tol2 * a * b) {
+      rotated = 1;
+      // With d = b - a, h = sqrt(d^2 + 4|gamma|^2) and u = |d| + h the
+      // rotation that zeroes the pair's inner product has
+      //   tan(theta) e = 2 sgn(d) gamma / u,   c = u w,   s e = 2 sgn(d) w gamma,
+      // w = 1/sqrt(u^2 + 4|gamma|^2) = 1/sqrt(2 h u) = (1/h) / sqrt(2 (1 + |d|/h)).
+      const double d = b - a;
+      const double s2 = fma(d, d, 4.0 * g2);
+      const double rh = rsqrt_nr(s2);
+      const double ad = fabs(d);
+      const double w = rh * rsqrt_nr(2.0 * fma(ad, rh, 1.0));
+      const double cs = fma(s2, rh, ad) * w;
+      const double sw2 = (d >= 0.0 ? 2.0 : -2.0) * w;
+      const double pr = sw2 * gr, pi = sw2 * gi;  // s e
+#pragma unroll
+      for (int i = 0; i < RPL; ++i) {
+        c2 xn, yn;
+        // x' = c x - conj(s e) y,  y' = (s e) x + c y
+        xn.x = cs * x[i].x - (pr * y[i].x + pi * y[i].y);
+        xn.y = cs * x[i].y - (pr * y[i].y - pi * y[i].x);
+        yn.x = cs * y[i].x + (pr * x[i].x - pi * x[i].y);
+        yn.y = cs * y[i].y + (pr * x[i].y + pi * x[i].x);
+        xc[i] = xn;
+        yc[i] = yn;
+      }
+    } else if (valid && !(a == a && b == b && g2 == g2)) {
+      flag_or(C, 4);
+    }
+    if (pp == 0) {
+      ib = (ib == m) ? 1 : ib + 1;
+    } else {
+      ia = (ia == m) ? 1 : ia + 1;
+      ib = (ib == m) ? 1 : ib + 1;
+    }
+    __syncthreads();
+  }
+  return rotated;
+}
+
+__device__ __forceinline__ int jacobi_lds(Ctx& C, sc2* X, int len, int ncol, int ldx, double thr2,
+                          int* sweeps_out) {
+  const int tid = C.tid, NT = C.nt;
+  const double tol = (double)len * 2.220446049250313e-16;
+  const double tol2 = tol * tol;
+  const int pad = pow2_at_least(len);
+  int n = ncol;
+  int sweeps = 0;
+  const int max_sweeps = C.md.max_sweeps;
+  for (int sw = 0; sw < max_sweeps && n >= 2; ++sw) {
+    const int P = (n + 1) >> 1;
+    // at most 8 rows per lane; the launch guarantees P * G <= NT for that
+    const int G = uniform(max(min(lanes_per(P, NT), pad), pad / 8));
+    int rotated;
+    switch (uniform(pad / G)) {
+      case 1: rotated = jacobi_sweep<1>(C, X, ldx, n, G, thr2, tol2); break;
+      case 2: rotated = jacobi_sweep<2>(C, X, ldx, n, G, thr2, tol2); break;
+      case 4: rotated = jacobi_sweep<4>(C, X, ldx, n, G, thr2, tol2); break;
+      default: rotated = jacobi_sweep<8>(C, X, ldx, n, G, thr2, tol2); break;
+    }
+    ++sweeps;
+    if (tid == 0) {
+      C.sstat[4] += 18LL * len * n * (n - 1);
+      C.sstat[6] += 2 * P - 1;  // rounds
+    }
+    const int any = __syncthreads_or(rotated);
+    // column norms; drop the ones at rounding level and pack the live ones
+    {
+      const int Gc = min(lanes_per(n, 2 * NT), pad);
+      const int Rc = pad / Gc;
+      const int gc = tid / Gc, qc = tid % Gc;
+      for (int c = gc; c < n; c += NT / Gc) {
+        const sc2* xc = X + c * ldx + qc * Rc;
+        double s = 0.0;
+        for (int i = 0; i < Rc; ++i) s += cabs2(xc[i]);
+        s = group_sum(s, Gc);
+        if (qc == 0) C.sig[c] = s;
+      }
+    }
+    __syncthreads();
+    if (tid == 0) {
+      int w = 0;
+      for (int c = 0; c < n; ++c) {
+        const int live = C.sig[c] > thr2;
+        C.perm[c] = live ? w : -1;
+        w += live;
+      }
+      C.si[1] = w;
+    }
+    __syncthreads();
+    const int nn = C.si[1];
+    if (nn < n) {
+      // move live column c to position perm[c] (<= c), in increasing order
+      // of c, so no source is overwritten before it is read
+      for (int c = 0; c < n; ++c) {
+        const int dst = C.perm[c];
+        if (dst >= 0 && dst != c) {
+          for (int row = tid; row < pad; row += NT) X[dst * ldx + row] = X[c * ldx + row];
+          if (tid == 0) C.sig[dst] = C.sig[c];
+          __syncthreads();
+        }
+      }
+      n = nn > 0 ? nn : 1;
+    }
+    if (!any) break;
+    if (sw + 1 == max_sweeps) {
+      if (tid == 0) flag_or(C, 2);
+      break;
+    }
+  }
+  if (sweeps == 0) {
+    // a single column: its norm was never computed
+    if (tid < 64) {
+      double s = 0.0;
+      for (int row = tid; row < len; row += 64) s += cabs2(X[row]);
+      s = wave_sum(s);
+      if (tid == 0) C.sig[0] = s;
+    }
+    __syncthreads();
+  }
+  for (int c = tid; c < n; c += NT) C.sig[c] = sqrt(C.sig[c]);
+  __syncthreads();
+  *sweeps_out = sweeps;
+  return n;
+}
+
+// Sort the n singular values (descending, ties by column index), choose the
+// kept count k by the truncation rule and compute 1/||sigma_{1..k}||.
+// n <= 64 (one wave decides).
+__device__ __forceinline__ void choose_k(Ctx& C, int n, int len, int capk) {
+  if (C.tid < 64) {
+    const int c = C.tid;
+    double v = (c < n) ? C.sig[c] : -1.0;
     if (!(v == v)) v = -1.0;
     int rank = 0;
-    for (int d = 0; d < nc; ++d) {
+#pragma unroll 4
+    for (int d = 0; d < n; ++d) {
       double w = C.sig[d];
       if (!(w == w)) w = -1.0;
       rank += (w > v) || (w == v && d < c);
     }
-    C.perm[rank] = c;
-  }
-  __syncthreads();
-  if (C.tid == 0) {
-    const double smax = C.sig[C.perm[0]];
-    int cnt = 0;
-    for (int c = 0; c < nc; ++c) cnt += (C.sig[c] >= C.md.eps * smax) ? 1 : 0;
-    int k = cnt < C.md.chi ? cnt : C.md.chi;
+    if (c < n) C.perm[rank] = c;
+    const unsigned long long key = wave_max_u64(c < n ? argmax_key(v, c) : 0ull);
+    const double smax = (key != 0ull) ? C.sig[63 - (int)(key & 63ull)] : 0.0;
+    const unsigned long long ball = __ballot(c < n && v >= C.md.eps * smax);
+    int k = __popcll(ball);
+    if (k > C.md.chi) k = C.md.chi;
     if (k < 1) k = 1;
-    const int lim = len < nc ? len : nc;
+    const int lim = len < n ? len : n;
     if (k > lim) k = lim;
+    int over = 0;
     if (k > capk) {
-      atomicOr(C.sflag, 1);
+      over = 1;
       k = capk;
     }
-    double s2 = 0.0;
-    for (int i = 0; i < k; ++i) {
-      const double s = C.sig[C.perm[i]];
-      s2 += s * s;
+    const double s2 = wave_sum((c < n && rank < k) ? v * v : 0.0);
+    if (c == 0) {
+      if (over) flag_or(C, 1);
+      if (!(smax > 0.0) || !(s2 == s2)) flag_or(C, 4);
+      C.sk[0] = k;
+      C.sinv[0] = (C.md.renorm && s2 > 0.0) ? 1.0 / sqrt(s2) : 1.0;
+      if (k > C.sstat[0]) C.sstat[0] = k;
     }
-    if (!(smax > 0.0) || !(s2 == s2)) atomicOr(C.sflag, 4);
-    C.sk[0] = k;
-    C.sinv[0] = (C.md.renorm && s2 > 0.0) ? 1.0 / sqrt(s2) : 1.0;
-    if (k > C.sstat[0]) C.sstat[0] = k;
   }
   __syncthreads();
 }
@@ -336,7 +717,7 @@ __device__ void choose_k(Ctx& C, int nc, int len, int capk) {
 // Site tensor transfer between HBM (capacity layout) and LDS (packed), with a
 // single-site 2x2 gate applied on the physical index: out[a,s,c] = sum_t
 // G[s][t] in[a,t,c].
-__device__ void load_site(Ctx& C, c2* dst, const c2* site, int dl, int dr, int capr,
+__device__ __forceinline__ void load_site(Ctx& C, sc2* dst, const c2* site, int dl, int dr, int capr,
                           const M22& G) {
   const int n = dl * 2 * dr;
   for (int idx = C.tid; idx < n; idx += C.nt) {
@@ -346,10 +727,10 @@ __device__ void load_site(Ctx& C, c2* dst, const c2* site, int dl, int dr, int c
     const int c = rem - s * dr;
     const c2 x0 = site[(size_t)(a * 2 + 0) * capr + c];
     const c2 x1 = site[(size_t)(a * 2 + 1) * capr + c];
-    dst[idx] = cfma(G.m[2 * s + 1], x1, cmul(G.m[2 * s], x0));
+    dst[idx] = m22_row(G, s, x0, x1);
   }
 }
-__device__ void store_site(Ctx& C, c2* site, const c2* src, int dl, int dr, int capr,
+__device__ __forceinline__ void store_site(Ctx& C, c2* site, const sc2* src, int dl, int dr, int capr,
                            const M22& G) {
   const int n = dl * 2 * dr;
   for (int idx = C.tid; idx < n; idx += C.nt) {
@@ -359,7 +740,7 @@ __device__ void store_site(Ctx& C, c2* site, const c2* src, int dl, int dr, int 
     const int c = rem - s * dr;
     const c2 x0 = src[(a * 2 + 0) * dr + c];
     const c2 x1 = src[(a * 2 + 1) * dr + c];
-    site[(size_t)(a * 2 + s) * capr + c] = cfma(G.m[2 * s + 1], x1, cmul(G.m[2 * s], x0));
+    site[(size_t)(a * 2 + s) * capr + c] = m22_row(G, s, x0, x1);
   }
 }
 
@@ -373,13 +754,14 @@ __device__ void store_site(Ctx& C, c2* site, const c2* src, int dl, int dr, int 
 //   rtl: right factor V^dag is written to `iso` (site b+1), the centre
 //        U diag(s) (dl,2,k) is left in LC.
 // Returns k, the new bond dimension.
-__device__ int bond_split(Ctx& C, const c2* Lt, const c2* Rt, int dl, int dm, int dr,
+__device__ __forceinline__ int bond_split(Ctx& C, const sc2* Lt, const sc2* Rt, int dl, int dm, int dr,
                           double phi, bool ltr, c2* iso, int iso_capr, const M22& Gfin,
                           int capk) {
+  long long t0 = ph_now(C);
   const int len = ltr ? 2 * dl : 2 * dr;
   const int nc = ltr ? 2 * dr : 2 * dl;
-  const int ldx = len | 1;
-  c2* X = C.X;
+  const int ldx = pow2_at_least(len) + 1;
+  sc2* X = C.X;
   c2* X0 = C.X0;
   const double cp = cos(phi), sp = sin(phi);
   const c2 ph_same = cmk(cp, -sp);  // exp(-i phi)   (z_s z_s' = +1)
@@ -392,8 +774,8 @@ __device__ int bond_split(Ctx& C, const c2* Lt, const c2* Rt, int dl, int dm, in
     const int s = row & 1;
     const int s2 = col / dr;
     const int c = col - s2 * dr;
-    const c2* lp = Lt + row * dm;
-    const c2* rp = Rt + s2 * dr + c;
+    const sc2* lp = Lt + row * dm;
+    const sc2* rp = Rt + s2 * dr + c;
     c2 acc = cmk(0.0, 0.0);
     for (int b = 0; b < dm; ++b) acc = cfma(lp[b], rp[b * 2 * dr], acc);
     acc = cmul(acc, s == s2 ? ph_same : ph_diff);
@@ -406,19 +788,34 @@ __device__ int bond_split(Ctx& C, const c2* Lt, const c2* Rt, int dl, int dm, in
     }
   }
   __syncthreads();
-  const int sw = jacobi_lds(C, X, len, nc, ldx);
+  // Z = X^dag (nc x len, rows padded to pow2(nc)) in LC..LO, pivoted LQ ->
+  // L (len x rank) in X
+  sc2* Z = C.LC;
+  const int ldz = pow2_at_least(nc);
+  for (int idx = C.tid; idx < len * ldz; idx += C.nt) {
+    const int r = idx / ldz, c = idx - r * ldz;
+    Z[idx] = c < nc ? cconj(X[c * ldx + r]) : cmk(0.0, 0.0);
+  }
+  __syncthreads();
+  ph_add(C, kPhTheta, t0);
+  double thr2;
+  const int rank = lq_pivot(C, Z, nc, len, ldz, X, ldx, &thr2);
+  ph_add(C, kPhLQ, t0);
+  int sw = 0;
+  const int nlive = jacobi_lds(C, X, len, rank, ldx, thr2, &sw);
+  ph_add(C, kPhJacobi, t0);
   if (C.tid == 0) {
     if (sw > C.sstat[1]) C.sstat[1] = sw;
     C.sstat[2] += sw;
     C.sstat[3] += 1;
     C.sstat[5] += 32LL * dl * dr * dm;  // theta = Lt . Rt (complex MACs x 8)
   }
-  choose_k(C, nc, len, capk);
+  choose_k(C, nlive, len, capk);
   const int k = C.sk[0];
   const double inv = C.sinv[0];
   if (C.tid == 0) C.sstat[5] += 8LL * k * nc * len;  // Q^dag theta
   // Q_i = X_{perm i} / sig_{perm i}  -> LO  (len x k, column i at LO + i*len)
-  c2* Q = C.LO;
+  sc2* Q = C.LO;
   for (int idx = C.tid; idx < k * len; idx += C.nt) {
     const int i = idx / len;
     const int r = idx - i * len;
@@ -426,13 +823,17 @@ __device__ int bond_split(Ctx& C, const c2* Lt, const c2* Rt, int dl, int dm, in
     Q[idx] = cscale(X[c * ldx + r], 1.0 / C.sig[c]);
   }
   __syncthreads();
-  // Dm[i][c] = sum_r conj(Q_i[r]) X0_c[r]  -> new centre in LC
+  // the unrotated theta back from HBM into the (now free) Jacobi buffer
+  for (int idx = C.tid; idx < nc * ldx; idx += C.nt) X[idx] = X0[idx];
+  __syncthreads();
+  // Dm[i][c] = sum_r conj(Q_i[r]) theta_c[r]  -> new centre in LC
   for (int idx = C.tid; idx < k * nc; idx += C.nt) {
     const int i = idx / nc;
     const int c = idx - i * nc;
-    const c2* qi = Q + i * len;
-    const c2* xc = X0 + c * ldx;
+    const sc2* qi = Q + i * len;
+    const sc2* xc = X + c * ldx;
     c2 acc = cmk(0.0, 0.0);
+#pragma unroll 4
     for (int r = 0; r < len; ++r) acc = cfmac(qi[r], xc[r], acc);
     if (ltr)
       C.LC[i * nc + c] = cscale(acc, inv);
@@ -450,7 +851,7 @@ __device__ int bond_split(Ctx& C, const c2* Lt, const c2* Rt, int dl, int dm, in
       const int i = rem - s * k;
       const c2 q0 = Q[i * len + a * 2 + 0];
       const c2 q1 = Q[i * len + a * 2 + 1];
-      iso[(size_t)(a * 2 + s) * iso_capr + i] = cfma(Gfin.m[2 * s + 1], q1, cmul(Gfin.m[2 * s], q0));
+      iso[(size_t)(a * 2 + s) * iso_capr + i] = m22_row(Gfin, s, q0, q1);
     }
   } else {
     // site b+1: (k, 2, dr), A[i,s,c] = sum_t G[s][t] conj(Q_i[t*dr + c])
@@ -462,10 +863,11 @@ __device__ int bond_split(Ctx& C, const c2* Lt, const c2* Rt, int dl, int dm, in
       const int c = rem - s * dr;
       const c2 q0 = cconj(Q[i * len + c]);
       const c2 q1 = cconj(Q[i * len + dr + c]);
-      iso[(size_t)(i * 2 + s) * iso_capr + c] = cfma(Gfin.m[2 * s + 1], q1, cmul(Gfin.m[2 * s], q0));
+      iso[(size_t)(i * 2 + s) * iso_capr + c] = m22_row(Gfin, s, q0, q1);
     }
   }
   __syncthreads();
+  ph_add(C, kPhFinish, t0);
   return k;
 }
 
@@ -479,11 +881,11 @@ __device__ __forceinline__ const c2* gate_ptr(const c2* gates, int N, int l, int
 // rotated by G when it is first loaded and again when it is final for this
 // slice, so src -> dst realises G . trunc[Z . (G psi)] (Sec. II, Eq. 4, second
 // order).  For an adjoint slice G = R^dag and phi -> -phi.  src may equal dst.
-__device__ void slice_sweep(Ctx& C, const c2* src, const int* src_dims, c2* dst,
+__device__ __forceinline__ void slice_sweep(Ctx& C, const c2* src, const int* src_dims, c2* dst,
                             int* dst_dims, bool ltr, const c2* gates, int l, bool dag,
                             double sign, const double* uzz, const double* Jrow) {
   const int N = C.md.N;
-  const Layout& L = *C.L;
+  const sLayout& L = *C.L;
   for (int b = C.tid; b <= N; b += C.nt) C.sdims[b] = src_dims[b];
   __syncthreads();
   auto gate = [&](int j) {
@@ -501,8 +903,10 @@ __device__ void slice_sweep(Ctx& C, const c2* src, const int* src_dims, c2* dst,
     __syncthreads();
     for (int b = 0; b < N - 1; ++b) {
       const int dl = C.sdims[b], dm = C.sdims[b + 1], dr = C.sdims[b + 2];
+      long long tl = ph_now(C);
       load_site(C, C.LO, src + L.off[b + 1], dm, dr, L.cap[b + 2], gate(b + 1));
       __syncthreads();
+      ph_add(C, kPhLoad, tl);
       const int k = bond_split(C, C.LC, C.LO, dl, dm, dr, phase(b), true,
                                dst + L.off[b], L.cap[b + 1], gate(b), L.cap[b + 1]);
       if (C.tid == 0) C.sdims[b + 1] = k;
@@ -514,8 +918,10 @@ __device__ void slice_sweep(Ctx& C, const c2* src, const int* src_dims, c2* dst,
     __syncthreads();
     for (int b = N - 2; b >= 0; --b) {
       const int dl = C.sdims[b], dm = C.sdims[b + 1], dr = C.sdims[b + 2];
+      long long tl = ph_now(C);
       load_site(C, C.LO, src + L.off[b], dl, dm, L.cap[b + 1], gate(b));
       __syncthreads();
+      ph_add(C, kPhLoad, tl);
       const int k = bond_split(C, C.LO, C.LC, dl, dm, dr, phase(b), false,
                                dst + L.off[b + 1], L.cap[b + 2], gate(b + 1), L.cap[b + 1]);
       if (C.tid == 0) C.sdims[b + 1] = k;
@@ -544,14 +950,14 @@ __device__ __forceinline__ void adjoint_slice(Ctx& C, const c2* src, const int* 
 }
 
 // Copy one MPS between two capacity layouts (dims must fit the destination).
-__device__ void copy_mps(Ctx& C, const c2* src, const int* sdims_g, int sdcap, c2* dst,
-                         int* ddims_g, const Layout& Ld) {
+__device__ __forceinline__ void copy_mps(Ctx& C, const c2* src, const int* sdims_g, int sdcap, c2* dst,
+                         int* ddims_g, const sLayout& Ld) {
   const int N = C.md.N;
   for (int b = C.tid; b <= N; b += C.nt) {
     int d = sdims_g[b];
     const int lim = min(Ld.cap[b], bond_cap(N, sdcap, b));
     if (d > lim || d < 1 || ((b == 0 || b == N) && d != 1)) {
-      atomicOr(C.sflag, 1);
+      flag_or(C, 1);
       d = max(1, min(d, lim));
       if (b == 0 || b == N) d = 1;
     }
@@ -578,7 +984,7 @@ __device__ void copy_mps(Ctx& C, const c2* src, const int* sdims_g, int sdcap, c
 // LDS scratch (complex, cap = max capacity): E, F, Ep (cap^2 each), TF, TFp
 // (2 cap^2 each) -> 7 cap^2, aliased on LC/LO/X.
 struct EnvBufs {
-  c2 *E, *F, *Ep, *TF, *TFp;
+  sc2 *E, *F, *Ep, *TF, *TFp;
 };
 __device__ __forceinline__ EnvBufs env_bufs(Ctx& C) {
   const int c2n = C.cap * C.cap;
@@ -593,8 +999,8 @@ __device__ __forceinline__ EnvBufs env_bufs(Ctx& C) {
 
 // Left pass: E_{j+1} = sum_s B_j[s]^dag E_j A_j[s]; stores E_j (j = 0..N) to
 // envs (stride cap^2) when envs != nullptr.  Returns E_N = <bra|ket>.
-__device__ c2 left_envs(Ctx& C, const c2* bra, const int* bd, const Layout& Lb,
-                        const c2* ket, const int* kd, const Layout& Lk, c2* envs) {
+__device__ __forceinline__ c2 left_envs(Ctx& C, const c2* bra, const int* bd, const sLayout& Lb,
+                        const c2* ket, const int* kd, const sLayout& Lk, c2* envs) {
   const int N = C.md.N;
   const int cc = C.cap * C.cap;
   EnvBufs eb = env_bufs(C);

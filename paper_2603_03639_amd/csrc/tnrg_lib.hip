@@ -9,6 +9,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
 #include <string>
 
 #include "tnrg.h"
@@ -23,7 +24,7 @@ using namespace tnrg;
 //   dR/dux = -a ux f I - i (g ux n + f X),  dR/duy = -a uy f I - i (g uy n + f Y)
 // with n = ux X + uy Y, f = sin(a r)/r, g = f'(r)/r (Sec. III, Eq. 8 drive).
 // Near r = 0, f and g are evaluated from their Taylor series.
-__device__ void half_rotation_f_g(double a, double r, double* f, double* g) {
+__device__ __forceinline__ void half_rotation_f_g(double a, double r, double* f, double* g) {
   const double x = a * r;
   if (x < 0.1) {
     const double x2 = x * x;
@@ -91,41 +92,49 @@ struct Shared {
   int sflag;
   int sk;
   double sinv;
-  long long sstat[8];
+  double sd[4];
+  int si[4];
+  long long sstat[kStats];
 };
 
-__device__ Ctx make_ctx(Shared& sh, c2* dyn, int cap, const ModelDev& md, c2* X0) {
+__device__ __forceinline__ Ctx make_ctx(Shared& sh, c2* dyn, int cap, const ModelDev& md, c2* X0) {
   Ctx C;
   C.tid = threadIdx.x;
   C.nt = blockDim.x;
   C.cap = cap;
-  const int cc = cap * cap;
-  C.LC = dyn;
-  C.LO = dyn + 2 * cc;
-  C.X = dyn + 4 * cc;
-  double* d = reinterpret_cast<double*>(C.X + 2 * cap * (2 * cap + 1));
+  // buffers sized from P2 = pow2(2 cap) so padded columns always fit
+  int P2 = 1;
+  while (P2 < 2 * cap) P2 <<= 1;
+  const int half = P2 * P2 / 2;
+  sc2* base = (sc2*)dyn;
+  C.LC = base;
+  C.LO = base + half;
+  C.X = base + 2 * half;
+  sdbl* d = (sdbl*)(C.X + P2 * (P2 + 1));
   C.sig = d;
-  C.perm = reinterpret_cast<int*>(d + 2 * cap);
+  C.perm = (sint*)(d + P2);
   C.X0 = X0;
-  C.L = &sh.L;
-  C.sdims = sh.sdims;
+  C.L = (sLayout*)&sh.L;
+  C.sdims = (sint*)sh.sdims;
   C.md = md;
-  C.sflag = &sh.sflag;
-  C.sstat = sh.sstat;
-  C.red = sh.red;
-  C.sk = &sh.sk;
-  C.sinv = &sh.sinv;
+  C.sflag = (sint*)&sh.sflag;
+  C.sstat = (sll*)sh.sstat;
+  C.red = (sdbl*)sh.red;
+  C.sk = (sint*)&sh.sk;
+  C.sinv = (sdbl*)&sh.sinv;
+  C.sd = (sdbl*)sh.sd;
+  C.si = (sint*)sh.si;
   if (C.tid == 0) {
     sh.sflag = 0;
-    for (int q = 0; q < 8; ++q) sh.sstat[q] = 0;
+    for (int q = 0; q < kStats; ++q) sh.sstat[q] = 0;
   }
   return C;
 }
 
 static size_t dyn_lds_bytes(int cap) {
-  const size_t cc = (size_t)cap * cap;
-  return (4 * cc + (size_t)2 * cap * (2 * cap + 1)) * sizeof(c2) + (size_t)2 * cap * sizeof(double) +
-         (size_t)2 * cap * sizeof(int);
+  size_t P2 = 1;
+  while (P2 < (size_t)2 * cap) P2 <<= 1;
+  return (P2 * P2 + P2 * (P2 + 1)) * sizeof(c2) + P2 * sizeof(double) + P2 * sizeof(int);
 }
 
 // ============================================================================
@@ -144,16 +153,16 @@ struct GradOut {
   c2 O;
 };
 
-__device__ void right_insertions(Ctx& C, const c2* bra, const int* bd, const c2* ket,
-                                 const int* kd, const Layout& L, const c2* envs, int lb,
+__device__ __forceinline__ void right_insertions(Ctx& C, const c2* bra, const int* bd, const c2* ket,
+                                 const int* kd, const sLayout& L, const c2* envs, int lb,
                                  const c2* gates, GradOut go) {
   const int N = C.md.N, M = C.md.M;
   const int cc = C.cap * C.cap;
   const double dt = C.md.dt;
   EnvBufs eb = env_bufs(C);
-  c2* TF = eb.TF;
-  c2* TFp = eb.TFp;
-  c2* Tq = C.LO;  // two-site intermediate (2 cap^2)
+  sc2* TF = eb.TF;
+  sc2* TFp = eb.TFp;
+  sc2* Tq = C.LO;  // two-site intermediate (2 cap^2)
   if (C.tid == 0) eb.F[0] = cmk(1.0, 0.0);
   __syncthreads();
   for (int j = N - 1; j >= 0; --j) {
@@ -293,7 +302,7 @@ __device__ void right_insertions(Ctx& C, const c2* bra, const int* bd, const c2*
       }
     }
     __syncthreads();
-    c2* tmp = TF;
+    sc2* tmp = TF;
     TF = TFp;
     TFp = tmp;
   }
@@ -334,8 +343,9 @@ __global__ void __launch_bounds__(256) k_grape(GrapeArgs A) {
   const int N = A.md.N, M = A.md.M;
   char* base = A.traj_base + (size_t)t * A.traj_bytes;
   Ctx C = make_ctx(sh, dyn, A.dcap, A.md, reinterpret_cast<c2*>(base + A.off_x0));
-  layout_build(sh.L, N, A.dcap);
-  const Layout& L = sh.L;
+  layout_build(*(sLayout*)&sh.L, N, A.dcap);
+  const sLayout& L = *(sLayout*)&sh.L;
+  long long t_all = ph_now(C);
   auto slot = [&](int s) { return reinterpret_cast<c2*>(base + (size_t)s * A.slot_bytes); };
   auto sdim = [&](int s) {
     return reinterpret_cast<int*>(base + (size_t)s * A.slot_bytes + A.dims_off);
@@ -373,12 +383,15 @@ __global__ void __launch_bounds__(256) k_grape(GrapeArgs A) {
   GradOut go;
   go.g = g;
   go.dO = dO;
+  long long te = ph_now(C);
   go.O = left_envs(C, slot(s_b), sdim(s_b), L, slot(s_aM), sdim(s_aM), L, envs);
+  ph_add(C, kPhEnvL, te);
   if (C.tid == 0) {
     *reinterpret_cast<c2*>(base + A.off_O) = go.O;
     if (A.overlaps) A.overlaps[t] = go.O;
   }
   right_insertions(C, slot(s_b), sdim(s_b), slot(s_aM), sdim(s_aM), L, envs, M, A.gates, go);
+  ph_add(C, kPhEnvR, te);
   adjoint_slice(C, slot(s_b), sdim(s_b), slot(s_b), sdim(s_b), A.gates, M - 1, A.uzz, Jrow);
   // adjoint sweep, segment by segment from the last checkpoint
   for (int i = A.nck - 1; i >= 0; --i) {
@@ -391,16 +404,20 @@ __global__ void __launch_bounds__(256) k_grape(GrapeArgs A) {
     }
     for (int l = L1; l >= L0; --l) {
       const int ket = (l == L0) ? i : s_seg + (l - 1 - L0);
+      te = ph_now(C);
       left_envs(C, slot(s_b), sdim(s_b), L, slot(ket), sdim(ket), L, envs);
+      ph_add(C, kPhEnvL, te);
       right_insertions(C, slot(s_b), sdim(s_b), slot(ket), sdim(ket), L, envs, l, A.gates, go);
+      ph_add(C, kPhEnvR, te);
       if (l >= 1)
         adjoint_slice(C, slot(s_b), sdim(s_b), slot(s_b), sdim(s_b), A.gates, l - 1, A.uzz, Jrow);
     }
   }
   __syncthreads();
+  ph_add(C, kPhTotal, t_all);
   if (C.tid == 0) {
     A.flags[t] = sh.sflag;
-    for (int q = 0; q < 8; ++q) A.stats[(size_t)t * 8 + q] = sh.sstat[q];
+    for (int q = 0; q < kStats; ++q) A.stats[(size_t)t * kStats + q] = sh.sstat[q];
   }
 }
 
@@ -456,14 +473,14 @@ __global__ void __launch_bounds__(256) k_evolve(EvolveArgs A) {
   const int t = blockIdx.x;
   const int N = A.md.N;
   const int cap = A.dcap;
-  Ctx C = make_ctx(sh, dyn, cap, A.md, A.x0 + (size_t)t * 2 * cap * (2 * cap + 1));
-  layout_build(sh.L, N, cap);
+  Ctx C = make_ctx(sh, dyn, cap, A.md, A.x0 + (size_t)t * x_elems(cap));
+  layout_build(*(sLayout*)&sh.L, N, cap);
   c2* psi = A.data + (size_t)t * A.stride;
   int* d = A.dims + (size_t)t * (N + 1);
   const double* Jrow = A.J + (size_t)t * (N - 1);
   for (int b = C.tid; b <= N; b += C.nt) {
     const int db = d[b];
-    if (db > sh.L.cap[b] || db < 1 || ((b == 0 || b == N) && db != 1)) atomicOr(&sh.sflag, 1);
+    if (db > sh.L.cap[b] || db < 1 || ((b == 0 || b == N) && db != 1)) flag_or(C, 1);
   }
   __syncthreads();
   if (!sh.sflag) {
@@ -477,7 +494,7 @@ __global__ void __launch_bounds__(256) k_evolve(EvolveArgs A) {
   __syncthreads();
   if (C.tid == 0) {
     A.flags[t] = sh.sflag;
-    for (int q = 0; q < 8; ++q) A.stats[(size_t)t * 8 + q] = sh.sstat[q];
+    for (int q = 0; q < kStats; ++q) A.stats[(size_t)t * kStats + q] = sh.sstat[q];
   }
 }
 
@@ -505,11 +522,11 @@ __global__ void __launch_bounds__(256) k_overlap(OverlapArgs A) {
   const int t = blockIdx.x;
   const int N = A.md.N;
   Ctx C = make_ctx(sh, dyn, A.cap, A.md, nullptr);
-  layout_build(sh.L, N, A.kdcap);
-  layout_build(L2, N, A.bdcap);
+  layout_build(*(sLayout*)&sh.L, N, A.kdcap);
+  layout_build(*(sLayout*)&L2, N, A.bdcap);
   const int rb = t % A.nb;
-  const c2 o = left_envs(C, A.bra + (size_t)rb * A.bstride, A.bdims + (size_t)rb * (N + 1), L2,
-                         A.ket + (size_t)t * A.kstride, A.kdims + (size_t)t * (N + 1), sh.L,
+  const c2 o = left_envs(C, A.bra + (size_t)rb * A.bstride, A.bdims + (size_t)rb * (N + 1), *(sLayout*)&L2,
+                         A.ket + (size_t)t * A.kstride, A.kdims + (size_t)t * (N + 1), *(sLayout*)&sh.L,
                          nullptr);
   if (C.tid == 0) {
     A.out[t] = o;
@@ -558,6 +575,7 @@ int check_model(const tnrg_model* md, ModelDev* out) {
   d.eps = md->trunc_eps;
   d.renorm = md->renormalize ? 1 : 0;
   d.max_sweeps = md->max_sweeps > 0 ? md->max_sweeps : 40;
+  d.profile = md->profile ? 1 : 0;
   for (int b = 0; b < md->n - 1; ++b) {
     if (md->zz_mask[b]) d.zzm[b >> 6] |= 1ull << (b & 63);
     if (md->xt_mask[b]) d.xtm[b >> 6] |= 1ull << (b & 63);
@@ -577,14 +595,36 @@ int check_batch(const tnrg_mps_batch* b, int N, const char* name) {
 
 // Threads per workgroup for a capacity bucket: enough lanes for every
 // column pair of a (2 cap) x (2 cap) Jacobi round with >= 2 lanes per pair.
-int threads_for_cap(int cap) {
+// The launch plan (set by the autotuner through tnrg_plan_set_threads)
+// overrides this per capacity.
+std::atomic<int> g_plan_threads[kMaxSites + 1];
+
+// Fewest threads for capacity cap: every Jacobi round processes up to cap
+// column pairs with at least pow2(2 cap) / 8 lanes each (8 rows per lane).
+int min_threads(int cap) {
+  int p2 = 1;
+  while (p2 < 2 * cap) p2 <<= 1;
+  const int need = (p2 / 8 > 1 ? p2 / 8 : 1) * cap;
   int nt = 64;
-  while (nt < 256 && nt < 2 * cap) nt *= 2;
+  while (nt < need) nt *= 2;
   return nt;
+}
+
+int default_threads(int cap) { return min_threads(cap); }
+
+int threads_for_cap(int cap) {
+  if (cap >= 0 && cap <= kMaxSites) {
+    const int t = g_plan_threads[cap].load(std::memory_order_relaxed);
+    if (t >= min_threads(cap)) return t;
+  }
+  return default_threads(cap);
 }
 
 // Largest dynamic LDS a workgroup may use on gfx950.
 constexpr size_t kMaxDynLds = 160 * 1024 - sizeof(Shared) - 512;
+// The bond update keeps a (2 cap) x (2 cap) problem inside one wave's lane
+// range for its pivot search and sort.
+constexpr int kMaxCap = 32;
 
 struct GrapeLayout {
   int cs, nck, nslots, nctrl, dcap;
@@ -604,14 +644,14 @@ GrapeLayout grape_layout(const tnrg_model* md, int K, int R, int dcap, int cs) {
   g.dims_off = align256(elems * sizeof(c2));
   g.slot_bytes = align256(g.dims_off + (size_t)(N + 1) * sizeof(int));
   g.off_x0 = (size_t)g.nslots * g.slot_bytes;
-  g.off_env = g.off_x0 + align256((size_t)2 * dcap * (2 * dcap + 1) * sizeof(c2));
+  g.off_env = g.off_x0 + align256((size_t)x_elems(dcap) * sizeof(c2));
   g.off_O = g.off_env + align256((size_t)(N + 1) * dcap * dcap * sizeof(c2));
   g.off_g = g.off_O + 256;
   g.traj_bytes = align256(g.off_g + (size_t)g.nctrl * sizeof(double));
   const int nt = K * R;
   g.off_flags = 0;
   g.off_stats = align256((size_t)nt * sizeof(int));
-  g.off_gates = g.off_stats + align256((size_t)nt * 8 * sizeof(long long));
+  g.off_gates = g.off_stats + align256((size_t)nt * kStats * sizeof(long long));
   g.off_traj = g.off_gates + align256((size_t)M * N * 12 * sizeof(c2));
   g.total = g.off_traj + (size_t)nt * g.traj_bytes;
   return g;
@@ -636,6 +676,19 @@ int launch_gates(const tnrg_model* md, const double* ux, const double* uy, c2* g
 
 extern "C" {
 
+int tnrg_plan_set_threads(int32_t dcap, int32_t threads) {
+  if (dcap < 1 || dcap > kMaxSites) return fail(TNRG_EINVAL, "dcap = %d out of range", dcap);
+  if (threads != 0 && threads != 64 && threads != 128 && threads != 256)
+    return fail(TNRG_EINVAL, "threads = %d must be 0, 64, 128 or 256", threads);
+  g_plan_threads[dcap].store(threads, std::memory_order_relaxed);
+  return TNRG_OK;
+}
+
+int32_t tnrg_plan_threads(int32_t dcap) {
+  if (dcap < 1 || dcap > kMaxSites) return 0;
+  return threads_for_cap(dcap);
+}
+
 int32_t tnrg_bond_cap(int32_t n_sites, int32_t dcap, int32_t bond) {
   if (n_sites < 1 || dcap < 1 || bond < 0 || bond > n_sites) return 0;
   return bond_cap(n_sites, dcap, bond);
@@ -657,9 +710,9 @@ const char* tnrg_version(void) { return "tnrg 0.1 gfx950"; }
 size_t mps_evolve_workspace_bytes(const tnrg_model* md, int32_t n_traj, int32_t dcap) {
   if (!md || n_traj < 1 || dcap < 1) return 0;
   const size_t nt = (size_t)n_traj;
-  return align256(nt * sizeof(int)) + align256(nt * 8 * sizeof(long long)) +
+  return align256(nt * sizeof(int)) + align256(nt * kStats * sizeof(long long)) +
          align256((size_t)md->m * md->n * 12 * sizeof(c2)) +
-         nt * (size_t)2 * dcap * (2 * dcap + 1) * sizeof(c2);
+         nt * (size_t)x_elems(dcap) * sizeof(c2);
 }
 
 int mps_evolve(const tnrg_model* md, const double* ux, const double* uy, const double* uzz,
@@ -675,8 +728,8 @@ int mps_evolve(const tnrg_model* md, const double* ux, const double* uy, const d
   const size_t need = mps_evolve_workspace_bytes(md, psi->n_traj, psi->dcap);
   if (ws_bytes < need) return fail(TNRG_ENOMEM, "workspace %zu < %zu bytes", ws_bytes, need);
   const size_t lds = dyn_lds_bytes(psi->dcap);
-  if (lds > kMaxDynLds)
-    return fail(TNRG_EUNSUPPORTED, "dcap = %d needs %zu bytes of LDS", psi->dcap, lds);
+  if (lds > kMaxDynLds || psi->dcap > kMaxCap)
+    return fail(TNRG_EUNSUPPORTED, "dcap = %d is above the supported %d", psi->dcap, kMaxCap);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   char* w = static_cast<char*>(ws);
   const size_t nt = psi->n_traj;
@@ -686,7 +739,7 @@ int mps_evolve(const tnrg_model* md, const double* ux, const double* uy, const d
   A.J = J;
   A.flags = reinterpret_cast<int*>(w);
   A.stats = reinterpret_cast<long long*>(w + align256(nt * sizeof(int)));
-  c2* gates = reinterpret_cast<c2*>(w + align256(nt * sizeof(int)) + align256(nt * 8 * sizeof(long long)));
+  c2* gates = reinterpret_cast<c2*>(w + align256(nt * sizeof(int)) + align256(nt * kStats * sizeof(long long)));
   A.gates = gates;
   A.x0 = reinterpret_cast<c2*>(reinterpret_cast<char*>(gates) +
                                align256((size_t)md->m * md->n * 12 * sizeof(c2)));
@@ -711,7 +764,7 @@ size_t mps_overlap_workspace_bytes(int32_t n_traj, int32_t n_sites, int32_t dcap
   (void)n_sites;
   (void)dcap;
   if (n_traj < 1) return 0;
-  return align256((size_t)n_traj * sizeof(int)) + align256((size_t)n_traj * 8 * sizeof(long long));
+  return align256((size_t)n_traj * sizeof(int)) + align256((size_t)n_traj * kStats * sizeof(long long));
 }
 
 int mps_overlap(const tnrg_mps_batch* bra, const tnrg_mps_batch* ket, tnrg_c128* out, void* ws,
@@ -786,7 +839,8 @@ int grape_fidelity_grad(const tnrg_model* md, const double* ux, const double* uy
   const GrapeLayout G = grape_layout(md, K, R, cap, cs);
   if (ws_bytes < G.total) return fail(TNRG_ENOMEM, "workspace %zu < %zu bytes", ws_bytes, G.total);
   const size_t lds = dyn_lds_bytes(cap);
-  if (lds > kMaxDynLds) return fail(TNRG_EUNSUPPORTED, "dcap = %d needs %zu bytes of LDS", cap, lds);
+  if (lds > kMaxDynLds || cap > kMaxCap)
+    return fail(TNRG_EUNSUPPORTED, "dcap = %d is above the supported %d", cap, kMaxCap);
   if ((long long)K * R > 0x7fffffff) return fail(TNRG_EINVAL, "too many trajectories");
 
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
@@ -858,16 +912,21 @@ int tnrg_status(const void* ws, int32_t n_traj, int32_t* host_flags, int64_t* st
   for (int t = 0; t < n_traj; ++t) any |= f[t];
   if (host_flags) memcpy(host_flags, f, flags.size());
   if (stats) {
-    std::string st((size_t)n_traj * 8 * sizeof(long long), '\0');
+    std::string st((size_t)n_traj * kStats * sizeof(long long), '\0');
     e = hipMemcpy(&st[0], static_cast<const char*>(ws) + align256((size_t)n_traj * sizeof(int)),
                   st.size(), hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(e, "hipMemcpy(stats)");
     const long long* p = reinterpret_cast<const long long*>(st.data());
-    int64_t out[6] = {0, 0, 0, 0, 0, 0};
+    int64_t out[16];
+    memset(out, 0, sizeof out);
     for (int t = 0; t < n_traj; ++t) {
-      out[0] = std::max<int64_t>(out[0], p[8 * t]);
-      out[1] = std::max<int64_t>(out[1], p[8 * t + 1]);
-      for (int q = 2; q < 6; ++q) out[q] += p[8 * t + q];
+      const long long* q = p + (size_t)kStats * t;
+      out[0] = std::max<int64_t>(out[0], q[0]);
+      out[1] = std::max<int64_t>(out[1], q[1]);
+      for (int i = 2; i < 6; ++i) out[i] += q[i];
+      for (int i = 0; i < 8; ++i) out[6 + i] += q[8 + i];
+      out[14] += q[6];
+      out[15] += q[7];
     }
     memcpy(stats, out, sizeof out);
   }

@@ -20,6 +20,8 @@ LIB_PATH = os.path.join(_HERE, "_lib", "libtnrg.so")
 
 OK, EINVAL, ENOMEM, EHIP, ENOCONV, ENONFINITE, EOVERFLOW, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7
 FLAG_OVERFLOW, FLAG_NOCONV, FLAG_NONFINITE = 1, 2, 4
+PHASES = ("load", "theta", "lq", "jacobi", "finish", "env_left", "env_right", "total")
+CLOCK_HZ = 100e6  # constant-rate counter behind the phase ticks
 
 
 class TnrgError(RuntimeError):
@@ -47,6 +49,7 @@ class _Model(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("m", ctypes.c_int32), ("dt", ctypes.c_double),
                 ("chi", ctypes.c_int32), ("trunc_eps", ctypes.c_double),
                 ("renormalize", ctypes.c_int32), ("max_sweeps", ctypes.c_int32),
+                ("profile", ctypes.c_int32),
                 ("zz_mask", ctypes.POINTER(ctypes.c_uint8)),
                 ("xt_mask", ctypes.POINTER(ctypes.c_uint8))]
 
@@ -76,6 +79,8 @@ _SIGS = {
                                            _sz, _vp]),
     "tnrg_status": (ctypes.c_int, [_vp, _i32, ctypes.POINTER(ctypes.c_int32),
                                    ctypes.POINTER(ctypes.c_int64), _vp]),
+    "tnrg_plan_set_threads": (ctypes.c_int, [_i32, _i32]),
+    "tnrg_plan_threads": (_i32, [_i32]),
     "tnrg_last_error": (ctypes.c_char_p, []),
     "tnrg_version": (ctypes.c_char_p, []),
 }
@@ -116,6 +121,7 @@ class Model:
     eps: float = 1e-12
     renormalize: bool = True
     max_sweeps: int = 0
+    profile: bool = False
     zz_mask: Optional[np.ndarray] = None
     xt_mask: Optional[np.ndarray] = None
 
@@ -126,6 +132,7 @@ class Model:
                                   else np.zeros(self.N - 1), np.uint8)
         m = _Model(self.N, self.M, float(self.dt), self.chi, float(self.eps),
                    1 if self.renormalize else 0, int(self.max_sweeps),
+                   1 if self.profile else 0,
                    zz.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
                    xt.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)))
         m._keep = (zz, xt)
@@ -223,14 +230,16 @@ def _workspace(nbytes: int, device) -> torch.Tensor:
 
 def status(ws: torch.Tensor, n_traj: int, stream=None, raise_on_error=True):
     flags = np.zeros(n_traj, np.int32)
-    stats = np.zeros(6, np.int64)
+    stats = np.zeros(16, np.int64)
     rc = _lib.tnrg_status(_ptr(ws), n_traj,
                           flags.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
                           stats.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
                           _stream(stream))
     info = dict(rc=rc, flags=flags, max_dim=int(stats[0]), max_sweeps=int(stats[1]),
                 total_sweeps=int(stats[2]), n_svd=int(stats[3]),
-                jacobi_flops=int(stats[4]), contraction_flops=int(stats[5]))
+                jacobi_flops=int(stats[4]), contraction_flops=int(stats[5]),
+                phase_ticks=dict(zip(PHASES, (int(x) for x in stats[6:14]))),
+                jacobi_rounds=int(stats[14]), lq_steps=int(stats[15]))
     if raise_on_error and rc != OK:
         raise TnrgError(rc, _lib.tnrg_last_error().decode())
     return info
@@ -272,7 +281,7 @@ def mps_overlap(bra: MPSBatch, ket: MPSBatch, stream=None) -> torch.Tensor:
 
 # Capacity buckets tried in order when a bond outgrows the current one; the
 # last working bucket per problem shape is remembered (the chi-bucket plan).
-BUCKETS = (8, 12, 16, 24, 32, 48, 64, 96, 128)
+BUCKETS = (4, 8, 16, 32)
 _plan_cache = {}
 
 

@@ -1,0 +1,63 @@
+"""Launch-plan autotuner: workgroup size per capacity bucket.
+
+The persistent kernel runs one workgroup per trajectory.  With few
+trajectories per SIMD the bond update is latency-bound, and 2 or 4 waves per
+trajectory can hide latency better than one; which is fastest depends on the
+bond dimensions the workload reaches.  ``autotune`` times each candidate on a
+short prefix of the caller's own problem (same N, capacity, ensemble size) and
+stores the winner in the library's process-wide plan (tnrg_plan_set_threads).
+Results do not depend on the choice beyond rounding.
+"""
+from __future__ import annotations
+
+import time
+from typing import Dict, Sequence
+
+import torch
+
+from . import tnrg
+
+CANDIDATES = (64, 128, 256)
+_tuned: Dict[tuple, int] = {}
+
+
+def set_threads(dcap: int, threads: int) -> None:
+    tnrg._check(tnrg._lib.tnrg_plan_set_threads(dcap, threads))
+
+
+def threads(dcap: int) -> int:
+    return int(tnrg._lib.tnrg_plan_threads(dcap))
+
+
+def autotune(model: "tnrg.Model", ux, uy, uzz, J, inputs: "tnrg.MPSBatch",
+             targets: "tnrg.MPSBatch", dcap: int, slices: int = 16,
+             candidates: Sequence[int] = CANDIDATES, repeats: int = 1) -> dict:
+    """Pick the fastest workgroup size for ``dcap`` on a prefix of the problem."""
+    K, R = int(J.shape[0]), inputs.n_traj
+    key = (model.N, dcap, K * R, model.chi)
+    if key in _tuned:
+        set_threads(dcap, _tuned[key])
+        return {"threads": _tuned[key], "cached": True}
+    Ms = max(1, min(model.M, slices))
+    import dataclasses
+    sub = dataclasses.replace(model, M=Ms)
+    args = [a[:Ms].contiguous() for a in (ux, uy, uzz)] + [J]
+    times = {}
+    for nt in candidates:
+        set_threads(dcap, nt)
+        call = tnrg.GrapeCall(sub, K, R, inputs, targets, dcap, device=inputs.data.device)
+        call.run(*args)
+        torch.cuda.synchronize()
+        best = float("inf")
+        for _ in range(repeats):
+            t0 = time.perf_counter()
+            call.run(*args)
+            torch.cuda.synchronize()
+            best = min(best, time.perf_counter() - t0)
+        call.check()
+        times[nt] = best
+        del call
+    win = min(times, key=times.get)
+    set_threads(dcap, win)
+    _tuned[key] = win
+    return {"threads": win, "cached": False, "seconds": times, "slices": Ms}
