@@ -65,6 +65,29 @@ def cpu_baseline(name, n_traj, R):
             "seconds": secs}
 
 
+def sources_sha256():
+    """Hash of the library sources, to match stored counter runs to this build."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    files = sorted(glob.glob(os.path.join(ROOT, "paper_2603_03639_amd", "csrc", "*")))
+    for f in files + [os.path.join(ROOT, "include", "tnrg.h")]:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def stored_traffic(workload):
+    """HBM bytes per launch from the committed FETCH_SIZE/WRITE_SIZE runs, or
+    None when the kernel sources changed since those counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"k_grape_{workload}_hbm.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    return rec["bytes_per_launch"] if rec.get("sources_sha256") == sources_sha256() else None
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -73,6 +96,8 @@ def main():
     ap.add_argument("--workload", default="cnot_n50")
     ap.add_argument("--cpu-sample", type=int, default=4,
                     help="trajectories of the oracle timed on the host (0 disables)")
+    ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
+                    help="also run a plain device copy of this many MiB (counter calibration)")
     ap.add_argument("--profile", action="store_true",
                     help="one extra call with in-kernel phase timers")
     ap.add_argument("--plain", type=int, default=8,
@@ -144,11 +169,22 @@ def main():
     kern_ms = sum(lat) / len(lat)
     achieved = flops / (kern_ms / 1000.0) / 1e12
     roofline = {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
+                "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
+                "traffic": stored_traffic(args.workload),
                 "kernel": "k_grape", "flops_per_launch": flops,
                 "jacobi_flops_per_launch": info["jacobi_flops"],
                 "contraction_flops_per_launch": info["contraction_flops"],
                 "avg_launch_ms": kern_ms}
+
+    if args.copy_calib:
+        # a plain device copy of known size: the HBM counters of the profiled
+        # run are scaled by what they read for this kernel
+        src = torch.empty(args.copy_calib << 20, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy calibration: {args.copy_calib} MiB device-to-device")
+        del src, dst
 
     phases = None
     if args.profile:
