@@ -201,6 +201,8 @@ def main():
         phases["ns_per_jacobi_round"] = ticks["jacobi"] * ns / max(pinfo["jacobi_rounds"], 1)
         phases["ns_per_lq_step"] = ticks["lq"] * ns / max(pinfo["lq_steps"], 1)
         phases["ns_per_svd"] = (ticks["theta"] + ticks["lq"] + ticks["jacobi"] + ticks["finish"]) * ns / max(pinfo["n_svd"], 1)
+        phases["ns_per_jacobi_round_loop"] = pinfo["jacobi_round_ticks"] * ns / max(pinfo["jacobi_rounds"], 1)
+        phases["jacobi_sweep_end_share"] = pinfo["jacobi_sweep_end_ticks"] / max(ticks["jacobi"], 1)
         phases["rounds_per_svd"] = pinfo["jacobi_rounds"] / max(pinfo["n_svd"], 1)
         phases["lq_steps_per_svd"] = pinfo["lq_steps"] / max(pinfo["n_svd"], 1)
         log("phase fractions of the persistent kernel: " +

@@ -176,7 +176,7 @@ int grape_fidelity_grad(const tnrg_model *md, const double *ux,
  * flags that the last call on `ws` left (n_traj entries).  Copies them to
  * host_flags when non-NULL; returns TNRG_OK, or the error of the most
  * severe flag (OVERFLOW before NOCONV before NONFINITE).  stats (may be NULL)
- * receives 16 counts over all trajectories: {max bond dimension reached, max
+ * receives 18 counts over all trajectories: {max bond dimension reached, max
  * Jacobi sweeps of one SVD, total Jacobi sweeps, number of SVDs, Jacobi flops
  * (36 m n(n-1)/2 per sweep of an m x n matrix), contraction flops (two-site
  * products, projections and transfer environments, 8 per complex
@@ -184,7 +184,8 @@ int grape_fidelity_grad(const tnrg_model *md, const double *ux,
  * of a 100 MHz counter summed over workgroups for the phases {site load,
  * theta, LQ preconditioner, Jacobi, split finish, left environments, right
  * environments and insertions, whole kernel}, then {Jacobi rounds, LQ
- * preconditioner steps}.
+ * preconditioner steps}, then the clock ticks of {Jacobi rounds, Jacobi
+ * end-of-sweep work}.
  */
 int tnrg_status(const void *ws, int32_t n_traj, int32_t *host_flags,
                 int64_t *stats, tnrg_stream stream);

@@ -30,8 +30,9 @@ typedef TNRG_LDS int sint;
 typedef TNRG_LDS long long sll;
 
 constexpr int kMaxSites = 256;
-constexpr int kStats = 16;
-enum { kPhLoad = 8, kPhTheta, kPhLQ, kPhJacobi, kPhFinish, kPhEnvL, kPhEnvR, kPhTotal };
+constexpr int kStats = 24;
+enum { kPhLoad = 8, kPhTheta, kPhLQ, kPhJacobi, kPhFinish, kPhEnvL, kPhEnvR, kPhTotal,
+       kPhJacRounds = 16, kPhJacSweepEnd };
 constexpr int kMaxWaves = 16;
 
 // ----------------------------------------------------------------------------
@@ -134,9 +135,9 @@ __host__ __device__ __forceinline__ int bond_cap(int N, int dcap, int b) {
 }
 
 // Elements of the Jacobi working matrix for capacity cap: P2 (P2 + 1) with
-// P2 = pow2(2 cap) (padded columns plus one element of bank skew).
+// P2 = max(4, pow2(2 cap)) (padded columns plus one element of bank skew).
 __host__ __device__ inline long long x_elems(int cap) {
-  long long p = 1;
+  long long p = 4;
   while (p < 2LL * cap) p <<= 1;
   return p * (p + 1);
 }
@@ -169,7 +170,7 @@ __host__ __device__ inline long long site_offset_slow(int N, int dcap, int j) {
   return o;
 }
 
-// Per-workgroup context.  LDS buffers are sized from P2 = pow2(2 cap):
+// Per-workgroup context.  LDS buffers are sized from P2 = max(4, pow2(2 cap)):
 //   LC, LO : P2^2 / 2 complex each (centre tensor, other tensor / isometry Q;
 //            together the LQ working matrix)
 //   X      : P2 (P2 + 1) complex (Jacobi working matrix)
@@ -514,7 +515,8 @@ __device__ __forceinline__ int lq_pivot(Ctx& C, sc2* Z, int nz, int mz, int ldz,
 // order.  Returns the number of live columns (>= 1); sig[c] holds ||X_c|| for
 // those.  *sweeps_out receives the number of sweeps.
 template <int RPL>
-__device__ __forceinline__ int jacobi_sweep(Ctx& C, sc2* X, int ldx, int n, int G, double thr2, double tol2) {
+__device__ __forceinline__ int jacobi_sweep(Ctx& C, sc2* X, int ldx, int n, int G, double thr2,
+                                            double tol2, sc2* dummy) {
   const int tid = C.tid;
   const int P = (n + 1) >> 1;
   const int m = 2 * P - 1;
@@ -525,9 +527,11 @@ __device__ __forceinline__ int jacobi_sweep(Ctx& C, sc2* X, int ldx, int n, int 
   const bool slot_ok = pp < P;
   int rotated = 0;
   for (int r = 0; r < m; ++r) {
+    // idle slots work on two scratch columns nobody reads, so the round is
+    // straight-line code without lane masking
     const bool valid = slot_ok && ia < n && ib < n;
-    sc2* xc = X + (valid ? ia : 0) * ldx + r0;
-    sc2* yc = X + (valid ? ib : 0) * ldx + r0;
+    sc2* xc = (valid ? X + ia * ldx : dummy) + r0;
+    sc2* yc = (valid ? X + ib * ldx : dummy + G * RPL) + r0;
     c2 x[RPL], y[RPL];
 #pragma unroll
     for (int i = 0; i < RPL; ++i) {
@@ -547,34 +551,33 @@ __device__ __forceinline__ int jacobi_sweep(Ctx& C, sc2* X, int ldx, int n, int 
     gr = group_sum(gr, G);
     gi = group_sum(gi, G);
     const double g2 = fma(gr, gr, gi * gi);
-    if (valid && a > thr2 && b > thr2 && g2 > tol2 * a * b) {
-      rotated = 1;
-      // With d = b - a, h = sqrt(d^2 + 4|gamma|^2) and u = |d| + h the
-      // rotation that zeroes the pair's inner product has
-      //   tan(theta) e = 2 sgn(d) gamma / u,   c = u w,   s e = 2 sgn(d) w gamma,
-      // w = 1/sqrt(u^2 + 4|gamma|^2) = 1/sqrt(2 h u) = (1/h) / sqrt(2 (1 + |d|/h)).
-      const double d = b - a;
-      const double s2 = fma(d, d, 4.0 * g2);
-      const double rh = rsqrt_nr(s2);
-      const double ad = fabs(d);
-      const double w = rh * rsqrt_nr(2.0 * fma(ad, rh, 1.0));
-      const double cs = fma(s2, rh, ad) * w;
-      const double sw2 = (d >= 0.0 ? 2.0 : -2.0) * w;
-      const double pr = sw2 * gr, pi = sw2 * gi;  // s e
+    const bool rot = valid && a > thr2 && b > thr2 && g2 > tol2 * a * b;
+    rotated |= rot;
+    // With d = b - a, h = sqrt(d^2 + 4|gamma|^2) and u = |d| + h the
+    // rotation that zeroes the pair's inner product has
+    //   tan(theta) e = 2 sgn(d) gamma / u,   c = u w,   s e = 2 sgn(d) w gamma,
+    // w = 1/sqrt(u^2 + 4|gamma|^2) = 1/sqrt(2 h u) = (1/h) / sqrt(2 (1 + |d|/h)).
+    // A pair that is not rotated gets the identity (c = 1, s = 0).
+    const double d = b - a;
+    const double s2 = fma(d, d, 4.0 * g2);
+    const double rh = rsqrt_nr(s2);
+    const double ad = fabs(d);
+    const double w = rh * rsqrt_nr(2.0 * fma(ad, rh, 1.0));
+    const double cs = rot ? fma(s2, rh, ad) * w : 1.0;
+    const double sw2 = rot ? (d >= 0.0 ? 2.0 : -2.0) * w : 0.0;
+    const double pr = sw2 * gr, pi = sw2 * gi;  // s e
 #pragma unroll
-      for (int i = 0; i < RPL; ++i) {
-        c2 xn, yn;
-        // x' = c x - conj(s e) y,  y' = (s e) x + c y
-        xn.x = cs * x[i].x - (pr * y[i].x + pi * y[i].y);
-        xn.y = cs * x[i].y - (pr * y[i].y - pi * y[i].x);
-        yn.x = cs * y[i].x + (pr * x[i].x - pi * x[i].y);
-        yn.y = cs * y[i].y + (pr * x[i].y + pi * x[i].x);
-        xc[i] = xn;
-        yc[i] = yn;
-      }
-    } else if (valid && !(a == a && b == b && g2 == g2)) {
-      flag_or(C, 4);
+    for (int i = 0; i < RPL; ++i) {
+      c2 xn, yn;
+      // x' = c x - conj(s e) y,  y' = (s e) x + c y
+      xn.x = cs * x[i].x - (pr * y[i].x + pi * y[i].y);
+      xn.y = cs * x[i].y - (pr * y[i].y - pi * y[i].x);
+      yn.x = cs * y[i].x + (pr * x[i].x - pi * x[i].y);
+      yn.y = cs * y[i].y + (pr * x[i].y + pi * x[i].x);
+      xc[i] = xn;
+      yc[i] = yn;
     }
+    if (valid && !(a == a && b == b && g2 == g2)) flag_or(C, 4);
     if (pp == 0) {
       ib = (ib == m) ? 1 : ib + 1;
     } else {
@@ -587,85 +590,87 @@ __device__ __forceinline__ int jacobi_sweep(Ctx& C, sc2* X, int ldx, int n, int 
 }
 
 __device__ __forceinline__ int jacobi_lds(Ctx& C, sc2* X, int len, int ncol, int ldx, double thr2,
-                          int* sweeps_out) {
+                                          int* sweeps_out) {
   const int tid = C.tid, NT = C.nt;
   const double tol = (double)len * 2.220446049250313e-16;
   const double tol2 = tol * tol;
   const int pad = pow2_at_least(len);
+  // idle pair slots read and write two scratch columns of pad rows in the
+  // (free) LO buffer, which holds P2^2 / 2 >= 2 pad elements
+  sc2* dummy = C.LO;
   int n = ncol;
   int sweeps = 0;
   const int max_sweeps = C.md.max_sweeps;
+  // column norms of the first n columns into sig (squared)
+  auto norms = [&](int nn) {
+    const int Gc = min(lanes_per(nn, 2 * NT), pad);
+    const int Rc = pad / Gc;
+    const int gc = tid / Gc, qc = tid % Gc;
+    for (int c = gc; c < nn; c += NT / Gc) {
+      const sc2* xc = X + c * ldx + qc * Rc;
+      double s = 0.0;
+      for (int i = 0; i < Rc; ++i) s += cabs2(xc[i]);
+      s = group_sum(s, Gc);
+      if (qc == 0) C.sig[c] = s;
+    }
+  };
   for (int sw = 0; sw < max_sweeps && n >= 2; ++sw) {
     const int P = (n + 1) >> 1;
     // at most 8 rows per lane; the launch guarantees P * G <= NT for that
     const int G = uniform(max(min(lanes_per(P, NT), pad), pad / 8));
     int rotated;
+    long long tj = ph_now(C);
     switch (uniform(pad / G)) {
-      case 1: rotated = jacobi_sweep<1>(C, X, ldx, n, G, thr2, tol2); break;
-      case 2: rotated = jacobi_sweep<2>(C, X, ldx, n, G, thr2, tol2); break;
-      case 4: rotated = jacobi_sweep<4>(C, X, ldx, n, G, thr2, tol2); break;
-      default: rotated = jacobi_sweep<8>(C, X, ldx, n, G, thr2, tol2); break;
+      case 1: rotated = jacobi_sweep<1>(C, X, ldx, n, G, thr2, tol2, dummy); break;
+      case 2: rotated = jacobi_sweep<2>(C, X, ldx, n, G, thr2, tol2, dummy); break;
+      case 4: rotated = jacobi_sweep<4>(C, X, ldx, n, G, thr2, tol2, dummy); break;
+      default: rotated = jacobi_sweep<8>(C, X, ldx, n, G, thr2, tol2, dummy); break;
     }
     ++sweeps;
     if (tid == 0) {
       C.sstat[4] += 18LL * len * n * (n - 1);
       C.sstat[6] += 2 * P - 1;  // rounds
     }
+    ph_add(C, kPhJacRounds, tj);
     const int any = __syncthreads_or(rotated);
-    // column norms; drop the ones at rounding level and pack the live ones
-    {
-      const int Gc = min(lanes_per(n, 2 * NT), pad);
-      const int Rc = pad / Gc;
-      const int gc = tid / Gc, qc = tid % Gc;
-      for (int c = gc; c < n; c += NT / Gc) {
-        const sc2* xc = X + c * ldx + qc * Rc;
-        double s = 0.0;
-        for (int i = 0; i < Rc; ++i) s += cabs2(xc[i]);
-        s = group_sum(s, Gc);
-        if (qc == 0) C.sig[c] = s;
-      }
-    }
-    __syncthreads();
-    if (tid == 0) {
-      int w = 0;
-      for (int c = 0; c < n; ++c) {
-        const int live = C.sig[c] > thr2;
-        C.perm[c] = live ? w : -1;
-        w += live;
-      }
-      C.si[1] = w;
-    }
-    __syncthreads();
-    const int nn = C.si[1];
-    if (nn < n) {
-      // move live column c to position perm[c] (<= c), in increasing order
-      // of c, so no source is overwritten before it is read
-      for (int c = 0; c < n; ++c) {
-        const int dst = C.perm[c];
-        if (dst >= 0 && dst != c) {
-          for (int row = tid; row < pad; row += NT) X[dst * ldx + row] = X[c * ldx + row];
-          if (tid == 0) C.sig[dst] = C.sig[c];
-          __syncthreads();
+    if (sw == 0 && any) {
+      // after the first sweep, drop the columns that sank to rounding level
+      // and pack the live ones to the front in order
+      norms(n);
+      __syncthreads();
+      if (tid == 0) {
+        int w = 0;
+        for (int c = 0; c < n; ++c) {
+          const int live = C.sig[c] > thr2;
+          C.perm[c] = live ? w : -1;
+          w += live;
         }
+        C.si[1] = w;
       }
-      n = nn > 0 ? nn : 1;
+      __syncthreads();
+      const int nn = C.si[1];
+      if (nn < n) {
+        // move live column c to position perm[c] (<= c) in increasing order
+        // of c, so no source is overwritten before it is read
+        for (int c = 0; c < n; ++c) {
+          const int dst = C.perm[c];
+          if (dst >= 0 && dst != c) {
+            for (int row = tid; row < pad; row += NT) X[dst * ldx + row] = X[c * ldx + row];
+            __syncthreads();
+          }
+        }
+        n = nn > 0 ? nn : 1;
+      }
     }
+    ph_add(C, kPhJacSweepEnd, tj);
     if (!any) break;
     if (sw + 1 == max_sweeps) {
       if (tid == 0) flag_or(C, 2);
       break;
     }
   }
-  if (sweeps == 0) {
-    // a single column: its norm was never computed
-    if (tid < 64) {
-      double s = 0.0;
-      for (int row = tid; row < len; row += 64) s += cabs2(X[row]);
-      s = wave_sum(s);
-      if (tid == 0) C.sig[0] = s;
-    }
-    __syncthreads();
-  }
+  norms(n);
+  __syncthreads();
   for (int c = tid; c < n; c += NT) C.sig[c] = sqrt(C.sig[c]);
   __syncthreads();
   *sweeps_out = sweeps;

@@ -102,8 +102,8 @@ __device__ __forceinline__ Ctx make_ctx(Shared& sh, c2* dyn, int cap, const Mode
   C.tid = threadIdx.x;
   C.nt = blockDim.x;
   C.cap = cap;
-  // buffers sized from P2 = pow2(2 cap) so padded columns always fit
-  int P2 = 1;
+  // buffers sized from P2 = max(4, pow2(2 cap)) so padded columns always fit
+  int P2 = 4;
   while (P2 < 2 * cap) P2 <<= 1;
   const int half = P2 * P2 / 2;
   sc2* base = (sc2*)dyn;
@@ -132,7 +132,7 @@ __device__ __forceinline__ Ctx make_ctx(Shared& sh, c2* dyn, int cap, const Mode
 }
 
 static size_t dyn_lds_bytes(int cap) {
-  size_t P2 = 1;
+  size_t P2 = 4;
   while (P2 < (size_t)2 * cap) P2 <<= 1;
   return (P2 * P2 + P2 * (P2 + 1)) * sizeof(c2) + P2 * sizeof(double) + P2 * sizeof(int);
 }
@@ -917,7 +917,7 @@ int tnrg_status(const void* ws, int32_t n_traj, int32_t* host_flags, int64_t* st
                   st.size(), hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(e, "hipMemcpy(stats)");
     const long long* p = reinterpret_cast<const long long*>(st.data());
-    int64_t out[16];
+    int64_t out[18];
     memset(out, 0, sizeof out);
     for (int t = 0; t < n_traj; ++t) {
       const long long* q = p + (size_t)kStats * t;
@@ -927,6 +927,8 @@ int tnrg_status(const void* ws, int32_t n_traj, int32_t* host_flags, int64_t* st
       for (int i = 0; i < 8; ++i) out[6 + i] += q[8 + i];
       out[14] += q[6];
       out[15] += q[7];
+      out[16] += q[16];
+      out[17] += q[17];
     }
     memcpy(stats, out, sizeof out);
   }

@@ -230,7 +230,7 @@ def _workspace(nbytes: int, device) -> torch.Tensor:
 
 def status(ws: torch.Tensor, n_traj: int, stream=None, raise_on_error=True):
     flags = np.zeros(n_traj, np.int32)
-    stats = np.zeros(16, np.int64)
+    stats = np.zeros(18, np.int64)
     rc = _lib.tnrg_status(_ptr(ws), n_traj,
                           flags.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
                           stats.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
@@ -239,7 +239,8 @@ def status(ws: torch.Tensor, n_traj: int, stream=None, raise_on_error=True):
                 total_sweeps=int(stats[2]), n_svd=int(stats[3]),
                 jacobi_flops=int(stats[4]), contraction_flops=int(stats[5]),
                 phase_ticks=dict(zip(PHASES, (int(x) for x in stats[6:14]))),
-                jacobi_rounds=int(stats[14]), lq_steps=int(stats[15]))
+                jacobi_rounds=int(stats[14]), lq_steps=int(stats[15]),
+                jacobi_round_ticks=int(stats[16]), jacobi_sweep_end_ticks=int(stats[17]))
     if raise_on_error and rc != OK:
         raise TnrgError(rc, _lib.tnrg_last_error().decode())
     return info
