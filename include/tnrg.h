@@ -65,14 +65,16 @@ enum {
   TNRG_ENOCONV = -4,    /* Jacobi SVD hit max_sweeps (device flag) */
   TNRG_ENONFINITE = -5, /* non-finite value met (device flag) */
   TNRG_EOVERFLOW = -6,  /* a bond needed more than the capacity dcap */
-  TNRG_EUNSUPPORTED = -7
+  TNRG_EUNSUPPORTED = -7,
+  TNRG_ESTALE = -8      /* grape_backward without its grape_forward (device flag) */
 };
 
 /* Device status flag bits (per trajectory, in the workspace). */
 enum {
   TNRG_FLAG_OVERFLOW = 1,
   TNRG_FLAG_NOCONV = 2,
-  TNRG_FLAG_NONFINITE = 4
+  TNRG_FLAG_NONFINITE = 4,
+  TNRG_FLAG_STALE = 8
 };
 
 /* Problem statement (Sec. II-III).  Host struct; the masks are host arrays. */
@@ -172,10 +174,45 @@ int grape_fidelity_grad(const tnrg_model *md, const double *ux,
                         tnrg_stream stream);
 
 /*
+ * grape_forward / grape_backward -- the two halves of grape_fidelity_grad,
+ * for callers that need the fidelity without the gradient (line searches,
+ * finite differences) or that run the adjoint later, as the backward pass of
+ * an autograd graph.  The arguments mean what they mean for
+ * grape_fidelity_grad.
+ *   grape_forward: the forward propagation (Sec. II, Eq. 4) of every
+ *     trajectory, with the checkpoints every ckpt_stride slices kept in ws,
+ *     then F[1] and overlaps[K*R] (may be NULL).  About a third of the work
+ *     of grape_fidelity_grad.
+ *   grape_backward: the adjoint sweep (App. A) from the checkpoints a
+ *     grape_forward call left in ws; writes g_ux, g_uy, g_uzz and traj_dO
+ *     (may be NULL).  All arguments, and the contents of the control, J,
+ *     input and target buffers, must be those of that forward call; the
+ *     forward call leaves a fingerprint of the sizes, the model and the
+ *     buffer addresses in ws, and a backward call whose fingerprint differs
+ *     sets TNRG_FLAG_STALE (tnrg_status returns TNRG_ESTALE) and computes
+ *     nothing.  Values changed in place are not detected.  A grape_backward
+ *     call leaves ws valid for another grape_backward.
+ * The flags and counters read by tnrg_status after grape_backward cover both
+ * calls.
+ */
+int grape_forward(const tnrg_model *md, const double *ux, const double *uy,
+                  const double *uzz, int32_t K, const double *J, int32_t R,
+                  const tnrg_mps_batch *inputs, const tnrg_mps_batch *targets,
+                  int32_t dcap, int32_t ckpt_stride, double *F,
+                  tnrg_c128 *overlaps, void *ws, size_t ws_bytes,
+                  tnrg_stream stream);
+int grape_backward(const tnrg_model *md, const double *ux, const double *uy,
+                   const double *uzz, int32_t K, const double *J, int32_t R,
+                   const tnrg_mps_batch *inputs, const tnrg_mps_batch *targets,
+                   int32_t dcap, int32_t ckpt_stride, double *g_ux,
+                   double *g_uy, double *g_uzz, tnrg_c128 *traj_dO, void *ws,
+                   size_t ws_bytes, tnrg_stream stream);
+
+/*
  * tnrg_status -- synchronise `stream`, then read the per-trajectory device
  * flags that the last call on `ws` left (n_traj entries).  Copies them to
  * host_flags when non-NULL; returns TNRG_OK, or the error of the most
- * severe flag (OVERFLOW before NOCONV before NONFINITE).  stats (may be NULL)
+ * severe flag (OVERFLOW, NOCONV, NONFINITE, STALE in that order).  stats (may be NULL)
  * receives 18 counts over all trajectories: {max bond dimension reached, max
  * Jacobi sweeps of one SVD, total Jacobi sweeps, number of SVDs, Jacobi flops
  * (36 m n(n-1)/2 per sweep of an m x n matrix), contraction flops (two-site

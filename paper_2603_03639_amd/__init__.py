@@ -6,7 +6,8 @@ torch.autograd.Function whose backward pass is the adjoint kernel.
 """
 from . import tnrg  # noqa: F401  (raises ImportError when the library is missing)
 from .tnrg import (Model, MPSBatch, GrapeCall, TnrgError, grape_fidelity_grad,  # noqa: F401
-                   mps_evolve, mps_overlap)
+                   fidelity, mps_evolve, mps_overlap)
+from .autograd import EnsembleFidelity, ensemble_fidelity  # noqa: F401
 
-__all__ = ["tnrg", "Model", "MPSBatch", "GrapeCall", "TnrgError",
-           "grape_fidelity_grad", "mps_evolve", "mps_overlap"]
+__all__ = ["tnrg", "Model", "MPSBatch", "GrapeCall", "TnrgError", "grape_fidelity_grad",
+           "fidelity", "mps_evolve", "mps_overlap", "EnsembleFidelity", "ensemble_fidelity"]

@@ -333,7 +333,49 @@ struct GrapeArgs {
   size_t traj_bytes, slot_bytes, dims_off, off_x0, off_env, off_O, off_g;
   c2* overlaps;
   c2* traj_dO;
+  int mode;                // kModeForward | kModeBackward
+  unsigned long long tag;  // fingerprint of the call's arguments
 };
+
+constexpr int kModeForward = 1, kModeBackward = 2;
+
+// Adjoint sweep of one trajectory (App. A): insertions at boundary M with the
+// environments `envs` already built for <T|a_M>, then for l = M-1 .. 0 the
+// backward state b_{l+1} = U_{l+1}^dag b_{l+2} and the insertions at the
+// boundary pair (b_{l+1}, a_l), the a_l recomputed segment by segment from
+// the checkpoints a_0, a_cs, a_2cs, ...
+__device__ __forceinline__ void grape_adjoint(Ctx& C, const GrapeArgs& A, char* base, GradOut& go,
+                                              c2* envs, const double* Jrow, const sLayout& L) {
+  const int M = A.md.M;
+  auto slot = [&](int s) { return reinterpret_cast<c2*>(base + (size_t)s * A.slot_bytes); };
+  auto sdim = [&](int s) {
+    return reinterpret_cast<int*>(base + (size_t)s * A.slot_bytes + A.dims_off);
+  };
+  const int s_seg = A.nck, s_aM = A.nck + A.cs - 1, s_b = A.nck + A.cs + 1;
+  long long te = ph_now(C);
+  right_insertions(C, slot(s_b), sdim(s_b), slot(s_aM), sdim(s_aM), L, envs, M, A.gates, go);
+  ph_add(C, kPhEnvR, te);
+  adjoint_slice(C, slot(s_b), sdim(s_b), slot(s_b), sdim(s_b), A.gates, M - 1, A.uzz, Jrow);
+  for (int i = A.nck - 1; i >= 0; --i) {
+    const int L0 = i * A.cs;
+    const int L1 = min((i + 1) * A.cs, M) - 1;
+    for (int l = L0 + 1; l <= L1; ++l) {
+      const int src = (l - 1 == L0) ? i : s_seg + (l - 2 - L0);
+      const int dst = s_seg + (l - 1 - L0);
+      forward_slice(C, slot(src), sdim(src), slot(dst), sdim(dst), A.gates, l - 1, A.uzz, Jrow);
+    }
+    for (int l = L1; l >= L0; --l) {
+      const int ket = (l == L0) ? i : s_seg + (l - 1 - L0);
+      te = ph_now(C);
+      left_envs(C, slot(s_b), sdim(s_b), L, slot(ket), sdim(ket), L, envs);
+      ph_add(C, kPhEnvL, te);
+      right_insertions(C, slot(s_b), sdim(s_b), slot(ket), sdim(ket), L, envs, l, A.gates, go);
+      ph_add(C, kPhEnvR, te);
+      if (l >= 1)
+        adjoint_slice(C, slot(s_b), sdim(s_b), slot(s_b), sdim(s_b), A.gates, l - 1, A.uzz, Jrow);
+    }
+  }
+}
 
 __global__ void __launch_bounds__(256) k_grape(GrapeArgs A) {
   extern __shared__ __align__(16) c2 dyn[];
@@ -355,63 +397,62 @@ __global__ void __launch_bounds__(256) k_grape(GrapeArgs A) {
   c2* envs = reinterpret_cast<c2*>(base + A.off_env);
   double* g = reinterpret_cast<double*>(base + A.off_g);
   c2* dO = A.traj_dO ? A.traj_dO + (size_t)t * A.nctrl : nullptr;
+  const bool fwd = A.mode & kModeForward, bwd = A.mode & kModeBackward;
+  unsigned long long* tagp = reinterpret_cast<unsigned long long*>(base + A.off_O + sizeof(c2));
 
-  copy_mps(C, A.in_data + (size_t)r * A.in_stride, A.in_dims + (size_t)r * (N + 1), A.in_dcap,
-           slot(0), sdim(0), L);
-  copy_mps(C, A.tg_data + (size_t)r * A.tg_stride, A.tg_dims + (size_t)r * (N + 1), A.tg_dcap,
-           slot(s_b), sdim(s_b), L);
-  for (int i = C.tid; i < A.nctrl; i += C.nt) {
-    g[i] = 0.0;
-    if (dO) dO[i] = cmk(0.0, 0.0);
+  if (!fwd) {
+    // the adjoint sweep reads the checkpoints a forward call with the same
+    // arguments left in this workspace; it also keeps that call's flags and
+    // counters and adds its own
+    if (C.tid == 0) {
+      if (*tagp == A.tag) {
+        sh.sflag = A.flags[t] & ~TNRG_FLAG_STALE;
+        for (int q = 0; q < kStats; ++q) sh.sstat[q] = A.stats[(size_t)t * kStats + q];
+      } else {
+        sh.sflag = TNRG_FLAG_STALE;
+      }
+    }
+  }
+  if (bwd) {
+    for (int i = C.tid; i < A.nctrl; i += C.nt) {
+      g[i] = 0.0;
+      if (dO) dO[i] = cmk(0.0, 0.0);
+    }
   }
   __syncthreads();
-
-  // forward pass with checkpoints a_0, a_cs, a_2cs, ...
-  int cur = 0;
-  for (int l = 0; l < M; ++l) {
-    int dst;
-    if (l + 1 == M)
-      dst = s_aM;
-    else if ((l + 1) % A.cs == 0)
-      dst = (l + 1) / A.cs;
-    else
-      dst = s_work;
-    forward_slice(C, slot(cur), sdim(cur), slot(dst), sdim(dst), A.gates, l, A.uzz, Jrow);
-    cur = dst;
-  }
-  // boundary M: O = <T|a_M>
-  GradOut go;
-  go.g = g;
-  go.dO = dO;
-  long long te = ph_now(C);
-  go.O = left_envs(C, slot(s_b), sdim(s_b), L, slot(s_aM), sdim(s_aM), L, envs);
-  ph_add(C, kPhEnvL, te);
-  if (C.tid == 0) {
-    *reinterpret_cast<c2*>(base + A.off_O) = go.O;
-    if (A.overlaps) A.overlaps[t] = go.O;
-  }
-  right_insertions(C, slot(s_b), sdim(s_b), slot(s_aM), sdim(s_aM), L, envs, M, A.gates, go);
-  ph_add(C, kPhEnvR, te);
-  adjoint_slice(C, slot(s_b), sdim(s_b), slot(s_b), sdim(s_b), A.gates, M - 1, A.uzz, Jrow);
-  // adjoint sweep, segment by segment from the last checkpoint
-  for (int i = A.nck - 1; i >= 0; --i) {
-    const int L0 = i * A.cs;
-    const int L1 = min((i + 1) * A.cs, M) - 1;
-    for (int l = L0 + 1; l <= L1; ++l) {
-      const int src = (l - 1 == L0) ? i : s_seg + (l - 2 - L0);
-      const int dst = s_seg + (l - 1 - L0);
-      forward_slice(C, slot(src), sdim(src), slot(dst), sdim(dst), A.gates, l - 1, A.uzz, Jrow);
+  if (!(sh.sflag & TNRG_FLAG_STALE)) {
+    copy_mps(C, A.tg_data + (size_t)r * A.tg_stride, A.tg_dims + (size_t)r * (N + 1), A.tg_dcap,
+             slot(s_b), sdim(s_b), L);
+    if (fwd) {
+      copy_mps(C, A.in_data + (size_t)r * A.in_stride, A.in_dims + (size_t)r * (N + 1),
+               A.in_dcap, slot(0), sdim(0), L);
+      // forward pass with checkpoints a_0, a_cs, a_2cs, ...
+      int cur = 0;
+      for (int l = 0; l < M; ++l) {
+        int dst;
+        if (l + 1 == M)
+          dst = s_aM;
+        else if ((l + 1) % A.cs == 0)
+          dst = (l + 1) / A.cs;
+        else
+          dst = s_work;
+        forward_slice(C, slot(cur), sdim(cur), slot(dst), sdim(dst), A.gates, l, A.uzz, Jrow);
+        cur = dst;
+      }
     }
-    for (int l = L1; l >= L0; --l) {
-      const int ket = (l == L0) ? i : s_seg + (l - 1 - L0);
-      te = ph_now(C);
-      left_envs(C, slot(s_b), sdim(s_b), L, slot(ket), sdim(ket), L, envs);
-      ph_add(C, kPhEnvL, te);
-      right_insertions(C, slot(s_b), sdim(s_b), slot(ket), sdim(ket), L, envs, l, A.gates, go);
-      ph_add(C, kPhEnvR, te);
-      if (l >= 1)
-        adjoint_slice(C, slot(s_b), sdim(s_b), slot(s_b), sdim(s_b), A.gates, l - 1, A.uzz, Jrow);
+    // boundary M: O = <T|a_M> (recomputed bit for bit by a backward-only call)
+    GradOut go;
+    go.g = g;
+    go.dO = dO;
+    long long te = ph_now(C);
+    go.O = left_envs(C, slot(s_b), sdim(s_b), L, slot(s_aM), sdim(s_aM), L, envs);
+    ph_add(C, kPhEnvL, te);
+    if (fwd && C.tid == 0) {
+      *reinterpret_cast<c2*>(base + A.off_O) = go.O;
+      *tagp = A.tag;
+      if (A.overlaps) A.overlaps[t] = go.O;
     }
+    if (bwd) grape_adjoint(C, A, base, go, envs, Jrow, L);
   }
   __syncthreads();
   ph_add(C, kPhTotal, t_all);
@@ -440,7 +481,7 @@ __global__ void k_reduce(int n_traj, int nctrl, int MN, int MN1, const char* tra
     else
       guzz[c - 2 * MN] = s;
   }
-  if (c == 0) {
+  if (c == 0 && F) {
     double s = 0.0;
     for (int t = 0; t < n_traj; ++t) {
       const c2 o = *reinterpret_cast<const c2*>(traj_base + (size_t)t * traj_bytes + off_O);
@@ -816,18 +857,35 @@ size_t grape_workspace_bytes(const tnrg_model* md, int32_t K, int32_t R, int32_t
   return grape_layout(md, K, R, cap, cs).total;
 }
 
-int grape_fidelity_grad(const tnrg_model* md, const double* ux, const double* uy,
-                        const double* uzz, int32_t K, const double* J, int32_t R,
-                        const tnrg_mps_batch* inputs, const tnrg_mps_batch* targets,
-                        int32_t dcap, int32_t ckpt_stride, double* F, double* g_ux,
-                        double* g_uy, double* g_uzz, tnrg_c128* overlaps, tnrg_c128* traj_dO,
-                        void* ws, size_t ws_bytes, tnrg_stream stream) {
+}  // extern "C"
+
+namespace {
+
+// FNV-1a over the words that fix what a forward call leaves in the workspace.
+struct Fnv {
+  unsigned long long h = 1469598103934665603ull;
+  template <class T>
+  void add(const T& v) {
+    const unsigned char* p = reinterpret_cast<const unsigned char*>(&v);
+    for (size_t i = 0; i < sizeof(T); ++i) h = (h ^ p[i]) * 1099511628211ull;
+  }
+};
+
+int grape_launch(int mode, const tnrg_model* md, const double* ux, const double* uy,
+                 const double* uzz, int32_t K, const double* J, int32_t R,
+                 const tnrg_mps_batch* inputs, const tnrg_mps_batch* targets, int32_t dcap,
+                 int32_t ckpt_stride, double* F, double* g_ux, double* g_uy, double* g_uzz,
+                 tnrg_c128* overlaps, tnrg_c128* traj_dO, void* ws, size_t ws_bytes,
+                 tnrg_stream stream) {
   ModelDev d;
   int rc = check_model(md, &d);
   if (rc) return rc;
   if (K < 1 || R < 1) return fail(TNRG_EINVAL, "K = %d, R = %d must be >= 1", K, R);
   if (!ux || !uy || !uzz || !J) return fail(TNRG_EINVAL, "NULL controls or crosstalk");
-  if (!F || !g_ux || !g_uy || !g_uzz || !ws) return fail(TNRG_EINVAL, "NULL output or workspace");
+  if (!ws) return fail(TNRG_EINVAL, "NULL workspace");
+  if ((mode & kModeForward) && !F) return fail(TNRG_EINVAL, "NULL fidelity output");
+  if ((mode & kModeBackward) && (!g_ux || !g_uy || !g_uzz))
+    return fail(TNRG_EINVAL, "NULL gradient output");
   if ((rc = check_batch(inputs, md->n, "inputs"))) return rc;
   if ((rc = check_batch(targets, md->n, "targets"))) return rc;
   if (inputs->n_traj != R || targets->n_traj != R)
@@ -881,8 +939,18 @@ int grape_fidelity_grad(const tnrg_model* md, const double* ux, const double* uy
   A.off_g = G.off_g;
   A.overlaps = reinterpret_cast<c2*>(overlaps);
   A.traj_dO = reinterpret_cast<c2*>(traj_dO);
+  A.mode = mode;
+  {
+    Fnv f;
+    f.add(md->n), f.add(md->m), f.add(md->dt), f.add(md->chi), f.add(md->trunc_eps);
+    f.add(md->renormalize), f.add(d.max_sweeps);
+    for (int b = 0; b + 1 < md->n; ++b) f.add(md->zz_mask[b]), f.add(md->xt_mask[b]);
+    f.add(ux), f.add(uy), f.add(uzz), f.add(J), f.add(K), f.add(R), f.add(cap), f.add(cs);
+    f.add(inputs->data), f.add(targets->data), f.add(ws);
+    A.tag = f.h | 1ull;  // never 0, the value of a cleared workspace
+  }
 
-  launch_gates(md, ux, uy, gates, s);
+  if (mode & kModeForward) launch_gates(md, ux, uy, gates, s);
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_grape),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute(k_grape)");
@@ -890,12 +958,45 @@ int grape_fidelity_grad(const tnrg_model* md, const double* ux, const double* uy
   e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "k_grape launch");
   const int MN = md->m * md->n;
-  hipLaunchKernelGGL(k_reduce, dim3((G.nctrl + 255) / 256), dim3(256), 0, s, K * R, G.nctrl, MN,
-                     md->m * (md->n - 1), A.traj_base, G.traj_bytes, G.off_O, G.off_g, F, g_ux, g_uy,
-                     g_uzz);
+  const int nred = (mode & kModeBackward) ? G.nctrl : 0;
+  hipLaunchKernelGGL(k_reduce, dim3(std::max(1, (nred + 255) / 256)), dim3(256), 0, s, K * R,
+                     nred, MN, md->m * (md->n - 1), A.traj_base, G.traj_bytes, G.off_O, G.off_g,
+                     (mode & kModeForward) ? F : nullptr, g_ux, g_uy, g_uzz);
   e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "k_reduce launch");
   return TNRG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int grape_fidelity_grad(const tnrg_model* md, const double* ux, const double* uy,
+                        const double* uzz, int32_t K, const double* J, int32_t R,
+                        const tnrg_mps_batch* inputs, const tnrg_mps_batch* targets,
+                        int32_t dcap, int32_t ckpt_stride, double* F, double* g_ux,
+                        double* g_uy, double* g_uzz, tnrg_c128* overlaps, tnrg_c128* traj_dO,
+                        void* ws, size_t ws_bytes, tnrg_stream stream) {
+  return grape_launch(kModeForward | kModeBackward, md, ux, uy, uzz, K, J, R, inputs, targets,
+                      dcap, ckpt_stride, F, g_ux, g_uy, g_uzz, overlaps, traj_dO, ws, ws_bytes,
+                      stream);
+}
+
+int grape_forward(const tnrg_model* md, const double* ux, const double* uy, const double* uzz,
+                  int32_t K, const double* J, int32_t R, const tnrg_mps_batch* inputs,
+                  const tnrg_mps_batch* targets, int32_t dcap, int32_t ckpt_stride, double* F,
+                  tnrg_c128* overlaps, void* ws, size_t ws_bytes, tnrg_stream stream) {
+  return grape_launch(kModeForward, md, ux, uy, uzz, K, J, R, inputs, targets, dcap, ckpt_stride,
+                      F, nullptr, nullptr, nullptr, overlaps, nullptr, ws, ws_bytes, stream);
+}
+
+int grape_backward(const tnrg_model* md, const double* ux, const double* uy, const double* uzz,
+                   int32_t K, const double* J, int32_t R, const tnrg_mps_batch* inputs,
+                   const tnrg_mps_batch* targets, int32_t dcap, int32_t ckpt_stride,
+                   double* g_ux, double* g_uy, double* g_uzz, tnrg_c128* traj_dO, void* ws,
+                   size_t ws_bytes, tnrg_stream stream) {
+  return grape_launch(kModeBackward, md, ux, uy, uzz, K, J, R, inputs, targets, dcap, ckpt_stride,
+                      nullptr, g_ux, g_uy, g_uzz, nullptr, traj_dO, ws, ws_bytes, stream);
 }
 
 int tnrg_status(const void* ws, int32_t n_traj, int32_t* host_flags, int64_t* stats,
@@ -935,6 +1036,8 @@ int tnrg_status(const void* ws, int32_t n_traj, int32_t* host_flags, int64_t* st
   if (any & TNRG_FLAG_OVERFLOW) return fail(TNRG_EOVERFLOW, "a bond needed more than the capacity");
   if (any & TNRG_FLAG_NOCONV) return fail(TNRG_ENOCONV, "Jacobi SVD reached max_sweeps");
   if (any & TNRG_FLAG_NONFINITE) return fail(TNRG_ENONFINITE, "non-finite value met");
+  if (any & TNRG_FLAG_STALE)
+    return fail(TNRG_ESTALE, "grape_backward without a matching grape_forward in this workspace");
   return TNRG_OK;
 }
 

@@ -18,8 +18,9 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "_lib", "libtnrg.so")
 
-OK, EINVAL, ENOMEM, EHIP, ENOCONV, ENONFINITE, EOVERFLOW, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7
-FLAG_OVERFLOW, FLAG_NOCONV, FLAG_NONFINITE = 1, 2, 4
+(OK, EINVAL, ENOMEM, EHIP, ENOCONV, ENONFINITE, EOVERFLOW, EUNSUPPORTED,
+ ESTALE) = 0, -1, -2, -3, -4, -5, -6, -7, -8
+FLAG_OVERFLOW, FLAG_NOCONV, FLAG_NONFINITE, FLAG_STALE = 1, 2, 4, 8
 PHASES = ("load", "theta", "lq", "jacobi", "finish", "env_left", "env_right", "total")
 CLOCK_HZ = 100e6  # constant-rate counter behind the phase ticks
 
@@ -77,6 +78,10 @@ _SIGS = {
     "grape_fidelity_grad": (ctypes.c_int, [_MP, _dp, _dp, _dp, _i32, _dp, _i32, _BP, _BP,
                                            _i32, _i32, _dp, _dp, _dp, _dp, _vp, _vp, _vp,
                                            _sz, _vp]),
+    "grape_forward": (ctypes.c_int, [_MP, _dp, _dp, _dp, _i32, _dp, _i32, _BP, _BP, _i32, _i32,
+                                     _dp, _vp, _vp, _sz, _vp]),
+    "grape_backward": (ctypes.c_int, [_MP, _dp, _dp, _dp, _i32, _dp, _i32, _BP, _BP, _i32,
+                                      _i32, _dp, _dp, _dp, _vp, _vp, _sz, _vp]),
     "tnrg_status": (ctypes.c_int, [_vp, _i32, ctypes.POINTER(ctypes.c_int32),
                                    ctypes.POINTER(ctypes.c_int64), _vp]),
     "tnrg_plan_set_threads": (ctypes.c_int, [_i32, _i32]),
@@ -333,8 +338,63 @@ class GrapeCall:
             _ptr(self.overlaps), _ptr(self.traj_dO), _ptr(self.ws), self.ws.numel(),
             _stream(stream)))
 
+    def forward(self, ux, uy, uzz, J, stream=None):
+        """Forward propagation only: F and the overlaps; the checkpoints stay
+        in this call's workspace for ``backward()``."""
+        _check(_lib.grape_forward(
+            ctypes.byref(self.cm), _ptr(ux), _ptr(uy), _ptr(uzz), self.K, _ptr(J), self.R,
+            ctypes.byref(self._bin), ctypes.byref(self._btg), self.dcap, self.ckpt_stride,
+            _ptr(self.F), _ptr(self.overlaps), _ptr(self.ws), self.ws.numel(), _stream(stream)))
+
+    def backward(self, ux, uy, uzz, J, stream=None):
+        """Adjoint sweep from the checkpoints of the last ``forward()`` with
+        the same buffers: the gradient (and traj_dO when requested)."""
+        _check(_lib.grape_backward(
+            ctypes.byref(self.cm), _ptr(ux), _ptr(uy), _ptr(uzz), self.K, _ptr(J), self.R,
+            ctypes.byref(self._bin), ctypes.byref(self._btg), self.dcap, self.ckpt_stride,
+            _ptr(self.g_ux), _ptr(self.g_uy), _ptr(self.g_uzz), _ptr(self.traj_dO),
+            _ptr(self.ws), self.ws.numel(), _stream(stream)))
+
     def check(self, stream=None, raise_on_error=True):
         return status(self.ws, self.K * self.R, stream, raise_on_error)
+
+
+def prepare(model: Model, ux, uy, uzz, J, inputs: MPSBatch, targets: MPSBatch,
+            dcap: Optional[int] = None, ckpt_stride: int = 0, want_traj_dO: bool = False,
+            stream=None):
+    """Run the forward propagation in the smallest capacity bucket that
+    holds every bond (searching upward on overflow) and return the prepared
+    GrapeCall, its F and overlaps computed and its checkpoints ready for
+    ``backward()``."""
+    dev = inputs.data.device
+    K = int(J.shape[0])
+    R = inputs.n_traj
+    key = (model.N, model.M, model.chi, K, R)
+    start = dcap if dcap is not None else _plan_cache.get(key)
+    seq = [dcap] if dcap is not None else _bucket_sequence(model, start)
+    last = None
+    for cap in seq:
+        call = GrapeCall(model, K, R, inputs, targets, cap, ckpt_stride, want_traj_dO, dev)
+        call.forward(ux, uy, uzz, J, stream)
+        info = call.check(stream, raise_on_error=False)
+        if info["rc"] == EOVERFLOW and dcap is None:
+            last = info
+            continue
+        if info["rc"] != OK:
+            raise TnrgError(info["rc"], _lib.tnrg_last_error().decode())
+        _plan_cache[key] = cap
+        return call
+    raise TnrgError(EOVERFLOW, f"bond dimension exceeded every bucket up to chi ({last})")
+
+
+def fidelity(model: Model, ux, uy, uzz, J, inputs: MPSBatch, targets: MPSBatch,
+             dcap: Optional[int] = None, stream=None):
+    """Ensemble fidelity without the gradient (forward propagation only).
+    Returns (F, overlaps[K][R]) as device tensors."""
+    dev = inputs.data.device
+    ux, uy, uzz, J = (_f64(a, dev) for a in (ux, uy, uzz, J))
+    call = prepare(model, ux, uy, uzz, J, inputs, targets, dcap, stream=stream)
+    return call.F[0], call.overlaps.view(call.K, call.R)
 
 
 def grape_fidelity_grad(model: Model, ux, uy, uzz, J, inputs: MPSBatch, targets: MPSBatch,
