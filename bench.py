@@ -88,6 +88,117 @@ def stored_traffic(workload):
     return rec["bytes_per_launch"] if rec.get("sources_sha256") == sources_sha256() else None
 
 
+def _request_pool(P, W, dev, n, seed=4):
+    """Device-resident requests of the serving mix (distinct problems)."""
+    f = lambda a: torch_mod().as_tensor(a, dtype=torch_mod().float64, device=dev)
+    pool = []
+    for spec in W.serving_mix(n, seed=seed):
+        p = W.make_problem(**spec)
+        inputs = P.MPSBatch.from_product(p.inputs, device=dev)
+        tcap = max(max(A.shape[0] for A in T) for T in p.targets)
+        targets = P.MPSBatch.from_mps(p.targets, dcap=max(1, tcap), device=dev)
+        pool.append((spec, P.Model.from_problem(p), f(p.ux), f(p.uy), f(p.uzz), f(p.J),
+                     inputs, targets))
+    return pool
+
+
+def torch_mod():
+    import torch
+    return torch
+
+
+def serving_leg(P, W, dev, seconds, open_loop_seconds, pool_size, arena_gib, streams):
+    """Continuous-batching serving of the request mix (Poisson arrivals).
+
+    1. every pool request once alone, back to back through a one-stream
+       server: service times, capacity estimate, bucket plan warm-up;
+    2. a window at 0.7 x the measured capacity: p50/p99 latency and
+       throughput of completed requests;
+    3. an open-loop window at 200 requests/s: what was admitted, completed,
+       left queued (then cancelled) and how the queue grew.
+    Requests whose bonds outgrow every supported capacity bucket fail with
+    their status and are counted, not hidden.
+    """
+    import numpy as np
+    torch = torch_mod()
+    S = P.serve
+    pool = _request_pool(P, W, dev, pool_size)
+    mk = lambda i: S.Request(*pool[i][1:])
+    arena = int(arena_gib * (1 << 30))
+
+    # 1. alone, back to back
+    service, fails = [], {}
+    with S.Server(arena, n_streams=1) as srv:
+        for i in range(len(pool)):
+            srv.submit(mk(i))
+            c = srv.drain()[0]
+            if c["status"] == 0:
+                service.append(c["total_ms"])
+            else:
+                fails[pool[i][0]["task"] + f"/N{pool[i][0]['N']}"] = c["status"]
+    ok_idx = [i for i in range(len(pool)) if not any(
+        pool[i][0]["task"] + f"/N{pool[i][0]['N']}" == k for k in fails)]
+    mean_service = float(np.mean(service)) if service else float("nan")
+    log(f"serving: {len(service)} of {len(pool)} pool requests served alone, mean "
+        f"{mean_service:.1f} ms, failures {fails}")
+
+    def window(rate, secs, seed, cancel_at_end):
+        rng = np.random.default_rng(seed)
+        lat, statuses, qmax = [], {}, 0
+        sub = 0
+        with S.Server(arena, n_streams=streams) as srv:
+            t0 = time.perf_counter()
+            next_t = rng.exponential(1.0 / rate)
+            while True:
+                now = time.perf_counter() - t0
+                if now >= secs:
+                    break
+                while next_t <= now:
+                    srv.submit(mk(int(rng.choice(ok_idx))))
+                    sub += 1
+                    next_t += rng.exponential(1.0 / rate)
+                for c in srv.progress():
+                    statuses[c["status"]] = statuses.get(c["status"], 0) + 1
+                    if c["status"] == 0:
+                        lat.append(c["total_ms"])
+                qmax = max(qmax, srv.info()["queued"])
+                time.sleep(0.0005)
+            info_end = srv.info()
+            cancelled = srv.cancel_queued() if cancel_at_end else []
+            t_close = time.perf_counter() - t0
+            for c in srv.drain():
+                statuses[c["status"]] = statuses.get(c["status"], 0) + 1
+                if c["status"] == 0:
+                    lat.append(c["total_ms"])
+            elapsed = time.perf_counter() - t0
+            info = srv.info()
+        out = {"offered_rate": rate, "window_s": secs, "submitted": sub,
+               "completed_ok": len(lat), "status_counts": {str(k): v for k, v in statuses.items()},
+               "max_queue": qmax, "queued_at_window_end": info_end["queued"],
+               "running_at_window_end": info_end["running"], "cancelled": len(cancelled),
+               "elapsed_s": elapsed, "drain_s": elapsed - t_close,
+               "throughput_req_s": len(lat) / elapsed if elapsed > 0 else None,
+               "admitted": info["admitted"], "regrown": info["regrown"]}
+        if lat:
+            out["latency_ms"] = {"p50": percentile(lat, 50), "p99": percentile(lat, 99),
+                                 "mean": float(np.mean(lat))}
+        return out
+
+    capacity = 1000.0 / mean_service if service else 0.0
+    sustainable = window(0.7 * capacity, seconds, 41, cancel_at_end=False) if capacity else None
+    if sustainable:
+        log(f"serving at {0.7 * capacity:.2f} req/s: {sustainable}")
+    open_loop = window(200.0, open_loop_seconds, 42, cancel_at_end=True)
+    log(f"serving open loop at 200 req/s: {open_loop}")
+    return {"mix": "N in {10,20,30,50}, chi in {16,32,64,128}, K in {8,32,128}, M in 100..300, "
+                   "task in {X, CNOT, GHZ, Heisenberg N=20}",
+            "pool_requests": len(pool), "streams": streams, "arena_gib": arena_gib,
+            "alone": {"served": len(service), "failed": fails,
+                      "mean_service_ms": mean_service,
+                      "capacity_req_s_one_stream": capacity},
+            "sustainable": sustainable, "open_loop": open_loop}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -100,6 +211,12 @@ def main():
                     help="also run a plain device copy of this many MiB (counter calibration)")
     ap.add_argument("--profile", action="store_true",
                     help="one extra call with in-kernel phase timers")
+    ap.add_argument("--serve-seconds", type=float, default=20.0,
+                    help="length of the sustainable-rate serving window (0 disables serving)")
+    ap.add_argument("--serve-open-loop", type=float, default=3.0,
+                    help="length of the open-loop serving window at 200 requests/s")
+    ap.add_argument("--serve-pool", type=int, default=24,
+                    help="distinct requests drawn from the serving mix")
     ap.add_argument("--plain", type=int, default=8,
                     help="trajectories run one at a time for the plain GPU path (0 disables)")
     args = ap.parse_args()
@@ -232,6 +349,15 @@ def main():
                  "seconds": secs}
         log(f"plain one-trajectory-at-a-time path: {secs:.2f} s for {n} trajectories")
 
+    serving = None
+    if args.serve_seconds > 0:
+        try:
+            serving = serving_leg(P, W, dev, args.serve_seconds, args.serve_open_loop,
+                                  args.serve_pool, arena_gib=64.0, streams=4)
+        except Exception as exc:  # the headline line is printed regardless
+            serving = {"error": f"{type(exc).__name__}: {exc}"}
+            log(f"serving leg failed: {serving['error']}")
+
     cpu = None
     if args.cpu_sample > 0:
         log("timing the CPU oracle ...")
@@ -253,6 +379,7 @@ def main():
         "batched_vs_plain": (value / plain["value"]) if plain else None,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "serving": serving,
         "fidelity": F,
         "phases": phases,
         "jacobi": {"svds": info["n_svd"], "total_sweeps": info["total_sweeps"],

@@ -138,6 +138,7 @@ int mps_evolve(const tnrg_model *md, const double *ux, const double *uy,
  * matrices (Sec. II, Eq. 7 overlap).  bra->n_traj must divide ket->n_traj.
  * out is device [ket->n_traj].
  */
+/* dcap: the larger of the two batches' capacities. */
 size_t mps_overlap_workspace_bytes(int32_t n_traj, int32_t n_sites,
                                    int32_t dcap);
 int mps_overlap(const tnrg_mps_batch *bra, const tnrg_mps_batch *ket,
@@ -155,8 +156,10 @@ int mps_overlap(const tnrg_mps_batch *bra, const tnrg_mps_batch *ket,
  *   targets: R MPS, right-canonical with unit norm (sites 1..N-1
  *            right-isometric).
  *   dcap: capacity of the internal states (bond dimensions above it raise
- *         TNRG_FLAG_OVERFLOW); 0 selects min(chi, 2^(N/2)); at most 32
- *         (TNRG_EUNSUPPORTED above).
+ *         TNRG_FLAG_OVERFLOW); 0 selects min(chi, 2^(N/2)); at most 128
+ *         (TNRG_EUNSUPPORTED above).  Up to 32 the per-trajectory working
+ *         buffers of a bond update live in LDS; above 32 in a per-trajectory
+ *         region of the workspace (slower, for the rare large-bond cases).
  * Outputs (device): F[1]; g_ux[M][N], g_uy[M][N], g_uzz[M][N-1] (zero on
  * bonds without u^zz); overlaps[K*R] (may be NULL); traj_dO (may be NULL):
  * [K*R][2*M*N + M*(N-1)] complex dO/du per trajectory in the order ux, uy, uzz.
@@ -236,6 +239,80 @@ int tnrg_status(const void *ws, int32_t n_traj, int32_t *host_flags,
  */
 int tnrg_plan_set_threads(int32_t dcap, int32_t threads);
 int32_t tnrg_plan_threads(int32_t dcap);
+
+/*
+ * Serving runtime: a request loop that runs fidelity+gradient evaluations of
+ * concurrent optimisations (different N, chi, M, K, R) on one GPU with
+ * continuous batching.  Each request is one persistent grape_fidelity_grad
+ * launch; requests are admitted in arrival order as soon as a stream slot
+ * and a block of the caller's device arena large enough for the request's
+ * workspace are free, so requests that arrive while others run start at once
+ * and their kernels share the GPU.  A request that was passed over because
+ * its workspace did not fit is bypassed by at most max_bypass later ones.
+ * The capacity bucket of each request is searched like the Python binding
+ * does (4, 8, 16, 32, 64, 128 below min(chi, 2^(N/2)), then that value),
+ * starting from the last bucket that worked for the same (N, M, chi, K, R);
+ * a request whose bonds outgrow its bucket is requeued at the head with the
+ * next one.
+ *
+ * Ownership: the arena (device memory) belongs to the caller and must
+ * outlive the server; the server sub-allocates workspaces from it and
+ * allocates no device memory itself (it creates its streams and events and
+ * a pinned host buffer per stream for the device flags).  Every buffer a
+ * request points to (controls, J, inputs, targets, outputs) must stay valid
+ * until its completion has been returned.  The model and batch descriptors
+ * are copied at submission.  One host thread drives a server.
+ */
+typedef struct tnrg_server tnrg_server;
+
+typedef struct {
+  const tnrg_model *md;
+  const double *ux, *uy, *uzz; /* device controls [M][N], [M][N], [M][N-1] */
+  int32_t K;
+  const double *J; /* device [K][N-1] */
+  int32_t R;
+  const tnrg_mps_batch *inputs, *targets;
+  int32_t dcap;    /* 0: bucket search */
+  double *F;       /* device [1] */
+  double *g_ux, *g_uy, *g_uzz;
+  tnrg_c128 *overlaps; /* device [K*R] or NULL */
+} tnrg_request;
+
+typedef struct {
+  int64_t ticket;
+  int32_t status;   /* TNRG_OK or the error of the request */
+  int32_t dcap;     /* capacity bucket of the last launch */
+  int32_t launches; /* 1 + bucket regrowths */
+  int32_t reserved;
+  double queue_ms;  /* submission to first admission */
+  double total_ms;  /* submission to completion seen by progress */
+} tnrg_completion;
+
+typedef struct {
+  int32_t queued, running;
+  int64_t submitted, admitted, completed, regrown, cancelled;
+  size_t arena_bytes, arena_free, arena_largest_free;
+} tnrg_server_info;
+
+/* n_streams in 1..16; max_bypass >= 0. */
+int tnrg_server_create(void *arena, size_t arena_bytes, int32_t n_streams,
+                       int32_t max_bypass, tnrg_server **out);
+/* Validates and queues a request; *ticket identifies its completion.  Does
+ * not launch: tnrg_server_progress does. */
+int tnrg_server_submit(tnrg_server *s, const tnrg_request *req,
+                       int64_t *ticket);
+/* Non-blocking step of the loop: collects finished launches (regrowing
+ * buckets where needed), admits queued requests, and returns up to max_done
+ * completions in done[0..*n_done-1] (the rest wait for the next call). */
+int tnrg_server_progress(tnrg_server *s, tnrg_completion *done,
+                         int32_t max_done, int32_t *n_done);
+/* Drops every queued request that has not been admitted; their tickets go
+ * to tickets[0..*n-1] (up to max). */
+int tnrg_server_cancel_queued(tnrg_server *s, int64_t *tickets, int32_t max,
+                              int32_t *n);
+int tnrg_server_info_get(const tnrg_server *s, tnrg_server_info *info);
+/* Waits for the running launches, then frees the server. */
+int tnrg_server_destroy(tnrg_server *s);
 
 /* Thread-local description of the last non-OK return. */
 const char *tnrg_last_error(void);

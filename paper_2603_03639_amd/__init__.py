@@ -8,6 +8,8 @@ from . import tnrg  # noqa: F401  (raises ImportError when the library is missin
 from .tnrg import (Model, MPSBatch, GrapeCall, TnrgError, grape_fidelity_grad,  # noqa: F401
                    fidelity, mps_evolve, mps_overlap)
 from .autograd import EnsembleFidelity, ensemble_fidelity  # noqa: F401
+from . import serve  # noqa: F401
 
 __all__ = ["tnrg", "Model", "MPSBatch", "GrapeCall", "TnrgError", "grape_fidelity_grad",
-           "fidelity", "mps_evolve", "mps_overlap", "EnsembleFidelity", "ensemble_fidelity"]
+           "fidelity", "mps_evolve", "mps_overlap", "EnsembleFidelity", "ensemble_fidelity",
+           "serve"]

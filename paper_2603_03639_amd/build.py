@@ -7,8 +7,10 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB_DIR = os.path.join(HERE, "_lib")
 LIB_PATH = os.path.join(LIB_DIR, "libtnrg.so")
-SOURCES = [os.path.join(HERE, "csrc", "tnrg_lib.hip")]
+SOURCES = [os.path.join(HERE, "csrc", "tnrg_lib.hip"), os.path.join(HERE, "csrc", "tnrg_server.cpp")]
 HEADERS = [os.path.join(HERE, "csrc", "tnrg_device.hpp"),
+           os.path.join(HERE, "csrc", "tnrg_common.hpp"),
+           os.path.join(HERE, "csrc", "tnrg_kernels.inc"),
            os.path.join(ROOT, "include", "tnrg.h")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

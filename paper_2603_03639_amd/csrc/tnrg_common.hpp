@@ -1,0 +1,255 @@
+// Memory-space independent building blocks of the MPS robust-GRAPE hot path
+// for gfx950: complex arithmetic, 2x2 gates, the model and MPS layout seen by
+// the kernels, and wave-level DPP reductions.
+//
+// Method references (Le, Mintert, Ginossar): second-order slice of Sec. II,
+// Eq. 4 with SVD compression to a maximum bond size; ensemble state fidelity
+// of Sec. II, Eq. 7; adjoint gradient of App. A, Eqs. A1-A2.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tnrg {
+
+
+// Complex double as a clang vector of two doubles (x = real, y = imaginary):
+// a builtin type, usable in every address space, 16-byte aligned like the
+// {re, im} storage of complex128.
+typedef double c2 __attribute__((ext_vector_type(2)));
+
+constexpr int kMaxSites = 256;
+constexpr int kStats = 24;
+enum { kPhLoad = 8, kPhTheta, kPhLQ, kPhJacobi, kPhFinish, kPhEnvL, kPhEnvR, kPhTotal,
+       kPhJacRounds = 16, kPhJacSweepEnd };
+constexpr int kMaxWaves = 16;
+
+// ----------------------------------------------------------------------------
+// complex helpers (x = real, y = imaginary)
+__device__ __forceinline__ c2 cmk(double r, double i) {
+  c2 v;
+  v.x = r;
+  v.y = i;
+  return v;
+}
+__device__ __forceinline__ c2 cadd(c2 a, c2 b) { return cmk(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ c2 csub(c2 a, c2 b) { return cmk(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ c2 cconj(c2 a) { return cmk(a.x, -a.y); }
+__device__ __forceinline__ c2 cscale(c2 a, double s) { return cmk(a.x * s, a.y * s); }
+__device__ __forceinline__ c2 cmul(c2 a, c2 b) {
+  return cmk(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// acc + a * b
+__device__ __forceinline__ c2 cfma(c2 a, c2 b, c2 acc) {
+  acc.x = fma(a.x, b.x, acc.x);
+  acc.x = fma(-a.y, b.y, acc.x);
+  acc.y = fma(a.x, b.y, acc.y);
+  acc.y = fma(a.y, b.x, acc.y);
+  return acc;
+}
+// acc + conj(a) * b
+__device__ __forceinline__ c2 cfmac(c2 a, c2 b, c2 acc) {
+  acc.x = fma(a.x, b.x, acc.x);
+  acc.x = fma(a.y, b.y, acc.x);
+  acc.y = fma(a.x, b.y, acc.y);
+  acc.y = fma(-a.y, b.x, acc.y);
+  return acc;
+}
+__device__ __forceinline__ double cabs2(c2 a) { return fma(a.x, a.x, a.y * a.y); }
+
+// 2x2 complex matrix, row-major g[s][t] = m[2*s+t]
+struct M22 {
+  c2 m[4];
+};
+__device__ __forceinline__ M22 m22_load(const c2* p) {
+  M22 r;
+  r.m[0] = p[0]; r.m[1] = p[1]; r.m[2] = p[2]; r.m[3] = p[3];
+  return r;
+}
+__device__ __forceinline__ M22 m22_dag(const M22& a) {
+  M22 r;
+  r.m[0] = cconj(a.m[0]); r.m[1] = cconj(a.m[2]);
+  r.m[2] = cconj(a.m[1]); r.m[3] = cconj(a.m[3]);
+  return r;
+}
+// Row s of G applied to (x0, x1): G[s][0] x0 + G[s][1] x1, with selects
+// instead of a dynamically indexed register array.
+__device__ __forceinline__ c2 m22_row(const M22& G, int s, c2 x0, c2 x1) {
+  const c2 g0 = s ? G.m[2] : G.m[0];
+  const c2 g1 = s ? G.m[3] : G.m[1];
+  return cfma(g1, x1, cmul(g0, x0));
+}
+__device__ __forceinline__ M22 m22_mul(const M22& a, const M22& b) {
+  M22 r;
+  r.m[0] = cadd(cmul(a.m[0], b.m[0]), cmul(a.m[1], b.m[2]));
+  r.m[1] = cadd(cmul(a.m[0], b.m[1]), cmul(a.m[1], b.m[3]));
+  r.m[2] = cadd(cmul(a.m[2], b.m[0]), cmul(a.m[3], b.m[2]));
+  r.m[3] = cadd(cmul(a.m[2], b.m[1]), cmul(a.m[3], b.m[3]));
+  return r;
+}
+
+// ----------------------------------------------------------------------------
+// Problem statement as seen by the kernels (passed by value).
+struct ModelDev {
+  int N, M;
+  double dt;
+  int chi;
+  double eps;
+  int renorm;
+  int max_sweeps;
+  int profile;      // 1: accumulate phase clock ticks into the stats
+  uint64_t zzm[4];  // bit b: bond b carries u^zz
+  uint64_t xtm[4];  // bit b: bond b carries crosstalk J
+};
+__device__ __forceinline__ bool bit(const uint64_t* m, int b) {
+  // every word is read and the choice is made on values, never on an
+  // address, so the mask words (and the context holding them) stay in
+  // registers
+  const uint64_t w0 = m[0], w1 = m[1], w2 = m[2], w3 = m[3];
+  const int k = b >> 6;
+  uint64_t w = w0;
+  w = k == 1 ? w1 : w;
+  w = k == 2 ? w2 : w;
+  w = k == 3 ? w3 : w;
+  return (w >> (b & 63)) & 1ull;
+}
+
+// Capacity of bond b: min(dcap, 2^b, 2^(N-b)).
+__host__ __device__ __forceinline__ int bond_cap(int N, int dcap, int b) {
+  int c = dcap;
+  if (b < 30 && (1 << b) < c) c = 1 << b;
+  int rb = N - b;
+  if (rb < 30 && (1 << rb) < c) c = 1 << rb;
+  return c;
+}
+
+// Elements of the Jacobi working matrix for capacity cap: P2 (P2 + 1) with
+// P2 = max(4, pow2(2 cap)) (padded columns plus one element of bank skew).
+__host__ __device__ inline long long x_elems(int cap) {
+  long long p = 4;
+  while (p < 2LL * cap) p <<= 1;
+  return p * (p + 1);
+}
+
+// Fixed-capacity MPS layout, built in LDS at kernel start.
+struct Layout {
+  int N;
+  int dcap;
+  int cap[kMaxSites + 1];
+  long long off[kMaxSites + 1];  // off[N] = elements per trajectory
+};
+__host__ __device__ inline long long site_offset_slow(int N, int dcap, int j) {
+  long long o = 0;
+  for (int i = 0; i < j; ++i) o += (long long)bond_cap(N, dcap, i) * 2 * bond_cap(N, dcap, i + 1);
+  return o;
+}
+
+// ----------------------------------------------------------------------------
+// Butterfly sums over aligned groups of G lanes (G = 1, 2, ..., 64) with DPP
+// lane permutations.  Every step combines a lane with the partner of an
+// involution (row mirror, half-row mirror, xor 1, xor 2) as a + b on one side
+// and b + a on the other, so all G lanes end with bit-identical sums.
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, true);
+  return __hiloint2double(hi, lo);
+}
+constexpr int kDppXor1 = 0xB1;        // quad_perm [1,0,3,2]
+constexpr int kDppXor2 = 0x4E;        // quad_perm [2,3,0,1]
+constexpr int kDppHalfMirror = 0x141; // lane i <-> 7-i within 8
+constexpr int kDppMirror = 0x140;     // lane i <-> 15-i within 16
+
+__device__ __forceinline__ double group_sum(double v, int G) {
+  // groups of 32 and 64 lanes (the larger capacities) first combine across
+  // rows with lane shuffles, then within rows as below
+  if (G >= 64) v += __shfl_xor(v, 32, 64);
+  if (G >= 32) v += __shfl_xor(v, 16, 64);
+  if (G >= 16) v += dpp_d<kDppMirror>(v);
+  if (G >= 8) v += dpp_d<kDppHalfMirror>(v);
+  if (G >= 2) v += dpp_d<kDppXor1>(v);
+  if (G >= 4) v += dpp_d<kDppXor2>(v);
+  return v;
+}
+
+// Reciprocal square root and reciprocal from the hardware estimate refined by
+// one Newton step (the estimate's relative error is squared away), so the
+// rotation parameters cost two short dependent chains instead of the IEEE
+// sqrt/divide sequences.
+__device__ __forceinline__ double rsqrt_nr(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  const double e = fma(-x * y, y, 1.0);
+  return fma(0.5 * y, e, y);
+}
+__device__ __forceinline__ double rcp_nr(double x) {
+  const double y = __builtin_amdgcn_rcp(x);
+  const double e = fma(-x, y, 1.0);
+  return fma(y, e, y);
+}
+
+// Lanes per group so that n groups fit in NT lanes, at most 16.
+__device__ __forceinline__ int lanes_per(int n, int NT) {
+  int g = 1;
+  while (g < 16 && n * g * 2 <= NT) g <<= 1;
+  return g;
+}
+
+// Wave-uniform helpers built on DPP row operations and readlane.
+__device__ __forceinline__ double readlane_d(double v, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+  return __hiloint2double(hi, lo);
+}
+template <int CTRL>
+__device__ __forceinline__ unsigned long long dpp_u64(unsigned long long v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(v & 0xffffffffu), CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(v >> 32), CTRL, 0xF, 0xF, true);
+  return ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo;
+}
+__device__ __forceinline__ unsigned long long umax64(unsigned long long a, unsigned long long b) {
+  return a > b ? a : b;
+}
+// Max over the 64 lanes of a wave (all lanes active); wave-uniform result.
+__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long k) {
+  k = umax64(k, dpp_u64<kDppMirror>(k));
+  k = umax64(k, dpp_u64<kDppHalfMirror>(k));
+  k = umax64(k, dpp_u64<kDppXor1>(k));
+  k = umax64(k, dpp_u64<kDppXor2>(k));
+  unsigned long long m = 0;
+  for (int r = 0; r < 4; ++r) {
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(k & 0xffffffffu), 16 * r);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(k >> 32), 16 * r);
+    m = umax64(m, ((unsigned long long)hi << 32) | lo);
+  }
+  return m;
+}
+// Sum over the 64 lanes of a wave in a fixed order; wave-uniform result.
+__device__ __forceinline__ double wave_sum(double v) {
+  v = group_sum(v, 16);
+  return ((readlane_d(v, 0) + readlane_d(v, 16)) + readlane_d(v, 32)) + readlane_d(v, 48);
+}
+// Argmax key of a non-negative value at index c < 256: larger values win,
+// ties (to 2^-44 relative) go to the smaller index.
+__device__ __forceinline__ unsigned long long argmax_key(double v, int c) {
+  if (!(v >= 0.0)) return 0ull;
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  return (b & ~255ull) | (unsigned long long)(255 - c);
+}
+__device__ __forceinline__ int argmax_index(unsigned long long key) {
+  return 255 - (int)(key & 255ull);
+}
+
+// ----------------------------------------------------------------------------
+// Row blocks.  A column of n rows is padded with zero rows to a power of two
+// `pad` and split over G lanes, lane q owning the contiguous rows
+// q*RPL .. q*RPL+RPL-1 (RPL = pad / G, a compile-time constant of the inner
+// loops, so they are straight-line code with immediate LDS offsets).
+__device__ __forceinline__ int pow2_at_least(int n) {
+  int p = 1;
+  while (p < n) p <<= 1;
+  return p;
+}
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+
+}  // namespace tnrg

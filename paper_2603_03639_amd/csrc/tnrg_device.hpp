@@ -1,155 +1,35 @@
-// Device building blocks of the MPS robust-GRAPE hot path for gfx950.
+// Device building blocks of the MPS robust-GRAPE hot path for gfx950 that
+// touch the per-workgroup working buffers.
 //
 // One workgroup owns one trajectory (one crosstalk sample k and one input r).
-// Everything a bond update touches lives in LDS: the two site tensors, the
-// two-site matrix theta and the one-sided Jacobi working copy.  The MPS itself
-// lives in HBM in a fixed-capacity layout (see include/tnrg.h) and is streamed
-// site by site during a sweep, so a slice reads and writes every site once.
+// Everything a bond update touches -- the two site tensors, the two-site
+// matrix theta and the one-sided Jacobi working copy -- lives in one set of
+// working buffers.  The MPS itself lives in HBM in a fixed-capacity layout
+// (include/tnrg.h) and is streamed site by site during a sweep, so a slice
+// reads and writes every site once.
 //
-// Method references (Le, Mintert, Ginossar): second-order slice of Sec. II,
-// Eq. 4 with SVD compression to a maximum bond size; ensemble state fidelity
-// of Sec. II, Eq. 7; adjoint gradient of App. A, Eqs. A1-A2.
-#pragma once
+// This file is included once per memory space of the working buffers:
+// TNRG_NS names the namespace and TNRG_AS qualifies the buffer pointers.
+// With TNRG_AS = address_space(3) the buffers are LDS and every access
+// compiles to ds_read / ds_write (capacities up to 32); with TNRG_AS empty
+// they are per-workgroup global scratch reached through flat pointers (the
+// larger capacities, whose working set exceeds the 160 KB of LDS).
+#include "tnrg_common.hpp"
 
-#include <hip/hip_runtime.h>
-#include <stdint.h>
+#if !defined(TNRG_NS) || !defined(TNRG_AS)
+#error "define TNRG_NS and TNRG_AS before including tnrg_device.hpp"
+#endif
 
-namespace tnrg {
+namespace TNRG_NS {
 
-// Complex double as a clang vector of two doubles (x = real, y = imaginary):
-// a builtin type, usable in every address space, 16-byte aligned like the
-// {re, im} storage of complex128.
-typedef double c2 __attribute__((ext_vector_type(2)));
+using namespace tnrg;
 
-// LDS-qualified types: pointers into workgroup memory compile to ds_read /
-// ds_write instead of flat accesses.
-#define TNRG_LDS __attribute__((address_space(3)))
-typedef TNRG_LDS c2 sc2;
-typedef TNRG_LDS double sdbl;
-typedef TNRG_LDS int sint;
-typedef TNRG_LDS long long sll;
+typedef TNRG_AS c2 sc2;
+typedef TNRG_AS double sdbl;
+typedef TNRG_AS int sint;
+typedef TNRG_AS long long sll;
 
-constexpr int kMaxSites = 256;
-constexpr int kStats = 24;
-enum { kPhLoad = 8, kPhTheta, kPhLQ, kPhJacobi, kPhFinish, kPhEnvL, kPhEnvR, kPhTotal,
-       kPhJacRounds = 16, kPhJacSweepEnd };
-constexpr int kMaxWaves = 16;
-
-// ----------------------------------------------------------------------------
-// complex helpers (x = real, y = imaginary)
-__device__ __forceinline__ c2 cmk(double r, double i) {
-  c2 v;
-  v.x = r;
-  v.y = i;
-  return v;
-}
-__device__ __forceinline__ c2 cadd(c2 a, c2 b) { return cmk(a.x + b.x, a.y + b.y); }
-__device__ __forceinline__ c2 csub(c2 a, c2 b) { return cmk(a.x - b.x, a.y - b.y); }
-__device__ __forceinline__ c2 cconj(c2 a) { return cmk(a.x, -a.y); }
-__device__ __forceinline__ c2 cscale(c2 a, double s) { return cmk(a.x * s, a.y * s); }
-__device__ __forceinline__ c2 cmul(c2 a, c2 b) {
-  return cmk(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
-}
-// acc + a * b
-__device__ __forceinline__ c2 cfma(c2 a, c2 b, c2 acc) {
-  acc.x = fma(a.x, b.x, acc.x);
-  acc.x = fma(-a.y, b.y, acc.x);
-  acc.y = fma(a.x, b.y, acc.y);
-  acc.y = fma(a.y, b.x, acc.y);
-  return acc;
-}
-// acc + conj(a) * b
-__device__ __forceinline__ c2 cfmac(c2 a, c2 b, c2 acc) {
-  acc.x = fma(a.x, b.x, acc.x);
-  acc.x = fma(a.y, b.y, acc.x);
-  acc.y = fma(a.x, b.y, acc.y);
-  acc.y = fma(-a.y, b.x, acc.y);
-  return acc;
-}
-__device__ __forceinline__ double cabs2(c2 a) { return fma(a.x, a.x, a.y * a.y); }
-
-// 2x2 complex matrix, row-major g[s][t] = m[2*s+t]
-struct M22 {
-  c2 m[4];
-};
-__device__ __forceinline__ M22 m22_load(const c2* p) {
-  M22 r;
-  r.m[0] = p[0]; r.m[1] = p[1]; r.m[2] = p[2]; r.m[3] = p[3];
-  return r;
-}
-__device__ __forceinline__ M22 m22_dag(const M22& a) {
-  M22 r;
-  r.m[0] = cconj(a.m[0]); r.m[1] = cconj(a.m[2]);
-  r.m[2] = cconj(a.m[1]); r.m[3] = cconj(a.m[3]);
-  return r;
-}
-// Row s of G applied to (x0, x1): G[s][0] x0 + G[s][1] x1, with selects
-// instead of a dynamically indexed register array.
-__device__ __forceinline__ c2 m22_row(const M22& G, int s, c2 x0, c2 x1) {
-  const c2 g0 = s ? G.m[2] : G.m[0];
-  const c2 g1 = s ? G.m[3] : G.m[1];
-  return cfma(g1, x1, cmul(g0, x0));
-}
-__device__ __forceinline__ M22 m22_mul(const M22& a, const M22& b) {
-  M22 r;
-  r.m[0] = cadd(cmul(a.m[0], b.m[0]), cmul(a.m[1], b.m[2]));
-  r.m[1] = cadd(cmul(a.m[0], b.m[1]), cmul(a.m[1], b.m[3]));
-  r.m[2] = cadd(cmul(a.m[2], b.m[0]), cmul(a.m[3], b.m[2]));
-  r.m[3] = cadd(cmul(a.m[2], b.m[1]), cmul(a.m[3], b.m[3]));
-  return r;
-}
-
-// ----------------------------------------------------------------------------
-// Problem statement as seen by the kernels (passed by value).
-struct ModelDev {
-  int N, M;
-  double dt;
-  int chi;
-  double eps;
-  int renorm;
-  int max_sweeps;
-  int profile;      // 1: accumulate phase clock ticks into the stats
-  uint64_t zzm[4];  // bit b: bond b carries u^zz
-  uint64_t xtm[4];  // bit b: bond b carries crosstalk J
-};
-__device__ __forceinline__ bool bit(const uint64_t* m, int b) {
-  // every word is read and the choice is made on values, never on an
-  // address, so the mask words (and the context holding them) stay in
-  // registers
-  const uint64_t w0 = m[0], w1 = m[1], w2 = m[2], w3 = m[3];
-  const int k = b >> 6;
-  uint64_t w = w0;
-  w = k == 1 ? w1 : w;
-  w = k == 2 ? w2 : w;
-  w = k == 3 ? w3 : w;
-  return (w >> (b & 63)) & 1ull;
-}
-
-// Capacity of bond b: min(dcap, 2^b, 2^(N-b)).
-__host__ __device__ __forceinline__ int bond_cap(int N, int dcap, int b) {
-  int c = dcap;
-  if (b < 30 && (1 << b) < c) c = 1 << b;
-  int rb = N - b;
-  if (rb < 30 && (1 << rb) < c) c = 1 << rb;
-  return c;
-}
-
-// Elements of the Jacobi working matrix for capacity cap: P2 (P2 + 1) with
-// P2 = max(4, pow2(2 cap)) (padded columns plus one element of bank skew).
-__host__ __device__ inline long long x_elems(int cap) {
-  long long p = 4;
-  while (p < 2LL * cap) p <<= 1;
-  return p * (p + 1);
-}
-
-// Fixed-capacity MPS layout, built in LDS at kernel start.
-struct Layout {
-  int N;
-  int dcap;
-  int cap[kMaxSites + 1];
-  long long off[kMaxSites + 1];  // off[N] = elements per trajectory
-};
-typedef TNRG_LDS Layout sLayout;
+typedef TNRG_AS Layout sLayout;
 __device__ __forceinline__ void layout_build(sLayout& L, int N, int dcap) {
   if (threadIdx.x == 0) {
     L.N = N;
@@ -163,11 +43,6 @@ __device__ __forceinline__ void layout_build(sLayout& L, int N, int dcap) {
     L.off[N] = o;
   }
   __syncthreads();
-}
-__host__ __device__ inline long long site_offset_slow(int N, int dcap, int j) {
-  long long o = 0;
-  for (int i = 0; i < j; ++i) o += (long long)bond_cap(N, dcap, i) * 2 * bond_cap(N, dcap, i + 1);
-  return o;
 }
 
 // Per-workgroup context.  LDS buffers are sized from P2 = max(4, pow2(2 cap)):
@@ -253,106 +128,6 @@ __device__ __forceinline__ void block_sum(Ctx& C, c2 (&v)[V]) {
 }
 
 // ----------------------------------------------------------------------------
-// Butterfly sums over aligned groups of G lanes (G = 1, 2, 4, 8, 16) with DPP
-// lane permutations.  Every step combines a lane with the partner of an
-// involution (row mirror, half-row mirror, xor 1, xor 2) as a + b on one side
-// and b + a on the other, so all G lanes end with bit-identical sums.
-template <int CTRL>
-__device__ __forceinline__ double dpp_d(double v) {
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, true);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, true);
-  return __hiloint2double(hi, lo);
-}
-constexpr int kDppXor1 = 0xB1;        // quad_perm [1,0,3,2]
-constexpr int kDppXor2 = 0x4E;        // quad_perm [2,3,0,1]
-constexpr int kDppHalfMirror = 0x141; // lane i <-> 7-i within 8
-constexpr int kDppMirror = 0x140;     // lane i <-> 15-i within 16
-
-__device__ __forceinline__ double group_sum(double v, int G) {
-  if (G >= 16) v += dpp_d<kDppMirror>(v);
-  if (G >= 8) v += dpp_d<kDppHalfMirror>(v);
-  if (G >= 2) v += dpp_d<kDppXor1>(v);
-  if (G >= 4) v += dpp_d<kDppXor2>(v);
-  return v;
-}
-
-// Reciprocal square root and reciprocal from the hardware estimate refined by
-// one Newton step (the estimate's relative error is squared away), so the
-// rotation parameters cost two short dependent chains instead of the IEEE
-// sqrt/divide sequences.
-__device__ __forceinline__ double rsqrt_nr(double x) {
-  const double y = __builtin_amdgcn_rsq(x);
-  const double e = fma(-x * y, y, 1.0);
-  return fma(0.5 * y, e, y);
-}
-__device__ __forceinline__ double rcp_nr(double x) {
-  const double y = __builtin_amdgcn_rcp(x);
-  const double e = fma(-x, y, 1.0);
-  return fma(y, e, y);
-}
-
-// Lanes per group so that n groups fit in NT lanes, at most 16.
-__device__ __forceinline__ int lanes_per(int n, int NT) {
-  int g = 1;
-  while (g < 16 && n * g * 2 <= NT) g <<= 1;
-  return g;
-}
-
-// Wave-uniform helpers built on DPP row operations and readlane.
-__device__ __forceinline__ double readlane_d(double v, int lane) {
-  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
-  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
-  return __hiloint2double(hi, lo);
-}
-template <int CTRL>
-__device__ __forceinline__ unsigned long long dpp_u64(unsigned long long v) {
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)(v & 0xffffffffu), CTRL, 0xF, 0xF, true);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(v >> 32), CTRL, 0xF, 0xF, true);
-  return ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo;
-}
-__device__ __forceinline__ unsigned long long umax64(unsigned long long a, unsigned long long b) {
-  return a > b ? a : b;
-}
-// Max over the 64 lanes of a wave (all lanes active); wave-uniform result.
-__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long k) {
-  k = umax64(k, dpp_u64<kDppMirror>(k));
-  k = umax64(k, dpp_u64<kDppHalfMirror>(k));
-  k = umax64(k, dpp_u64<kDppXor1>(k));
-  k = umax64(k, dpp_u64<kDppXor2>(k));
-  unsigned long long m = 0;
-  for (int r = 0; r < 4; ++r) {
-    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(k & 0xffffffffu), 16 * r);
-    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(k >> 32), 16 * r);
-    m = umax64(m, ((unsigned long long)hi << 32) | lo);
-  }
-  return m;
-}
-// Sum over the 64 lanes of a wave in a fixed order; wave-uniform result.
-__device__ __forceinline__ double wave_sum(double v) {
-  v = group_sum(v, 16);
-  return ((readlane_d(v, 0) + readlane_d(v, 16)) + readlane_d(v, 32)) + readlane_d(v, 48);
-}
-// Argmax key of a non-negative value at index c < 64: larger values win,
-// ties (to 2^-46 relative) go to the smaller index.
-__device__ __forceinline__ unsigned long long argmax_key(double v, int c) {
-  if (!(v >= 0.0)) return 0ull;
-  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
-  return (b & ~63ull) | (unsigned long long)(63 - c);
-}
-
-// ----------------------------------------------------------------------------
-// Row blocks.  A column of n rows is padded with zero rows to a power of two
-// `pad` and split over G lanes, lane q owning the contiguous rows
-// q*RPL .. q*RPL+RPL-1 (RPL = pad / G, a compile-time constant of the inner
-// loops, so they are straight-line code with immediate LDS offsets).
-__device__ __forceinline__ int pow2_at_least(int n) {
-  int p = 1;
-  while (p < n) p <<= 1;
-  return p;
-}
-__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
-
-// ----------------------------------------------------------------------------
 // Pivoted Householder LQ (QR with column pivoting of X^dag) as the
 // preconditioner of the one-sided Jacobi SVD.  Z (column-major, column r at
 // Z + r*ldz, ldz = pad(nz) rows with zero padding) holds X^dag: column r of Z
@@ -361,7 +136,7 @@ __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirs
 // written column-major into X (ldx, rows padded with zeros to pad(mz)); L has
 // the singular values and left singular vectors of X.  Columns of Z whose
 // remaining norm falls to thr2 = (len eps)^2 ||X||_F^2 stop the factorisation
-// (numerical rank).  Returns the rank (>= 1).  mz <= 64.
+// (numerical rank).  Returns the rank (>= 1).  mz <= 256.
 // Scratch: nrm = C.sig (remaining squared norms by logical column), pcol =
 // C.perm (logical -> physical column of Z).
 template <int RQ>
@@ -425,7 +200,9 @@ __device__ __forceinline__ int lq_pivot(Ctx& C, sc2* Z, int nz, int mz, int ldz,
   }
   __syncthreads();
   if (tid < 64) {
-    const double f2 = wave_sum(tid < mz ? nrm[tid] : 0.0);
+    double part = 0.0;
+    for (int c = tid; c < mz; c += 64) part += nrm[c];
+    const double f2 = wave_sum(part);
     if (tid == 0) {
       const double lt = (double)mz * 2.220446049250313e-16;
       sh_d[3] = lt * lt * f2;
@@ -438,9 +215,10 @@ __device__ __forceinline__ int lq_pivot(Ctx& C, sc2* Z, int nz, int mz, int ldz,
   int rank = steps;
   for (int j = 0; j < steps; ++j) {
     if (tid < 64) {
-      const unsigned long long key =
-          wave_max_u64((tid >= j && tid < mz) ? argmax_key(nrm[tid], tid) : 0ull);
-      const int best = 63 - (int)(key & 63ull);
+      unsigned long long kk = 0ull;
+      for (int c = tid; c < mz; c += 64) kk = umax64(kk, c >= j ? argmax_key(nrm[c], c) : 0ull);
+      const unsigned long long key = wave_max_u64(kk);
+      const int best = argmax_index(key);
       const double bv = nrm[best];
       if (tid == 0) {
         const int stop = !(key != 0ull && bv > thr2);
@@ -520,16 +298,13 @@ __device__ __forceinline__ int jacobi_sweep(Ctx& C, sc2* X, int ldx, int n, int 
   const int tid = C.tid;
   const int P = (n + 1) >> 1;
   const int m = 2 * P - 1;
-  const int pp = tid / G, q = tid % G;
+  const int grp = tid / G, q = tid % G;
+  const int ngrp = C.nt / G;
   const int r0 = q * RPL;
-  int ia = (pp == 0) ? 0 : 1 + pp;
-  int ib = (pp == 0) ? 1 : 1 + m - pp;
-  const bool slot_ok = pp < P;
   int rotated = 0;
-  for (int r = 0; r < m; ++r) {
-    // idle slots work on two scratch columns nobody reads, so the round is
-    // straight-line code without lane masking
-    const bool valid = slot_ok && ia < n && ib < n;
+  // one pair (ia, ib) of one round; idle slots work on two scratch columns
+  // nobody reads, so the round is straight-line code without lane masking
+  auto pair = [&](int ia, int ib, bool valid) {
     sc2* xc = (valid ? X + ia * ldx : dummy) + r0;
     sc2* yc = (valid ? X + ib * ldx : dummy + G * RPL) + r0;
     c2 x[RPL], y[RPL];
@@ -578,13 +353,39 @@ __device__ __forceinline__ int jacobi_sweep(Ctx& C, sc2* X, int ldx, int n, int 
       yc[i] = yn;
     }
     if (valid && !(a == a && b == b && g2 == g2)) flag_or(C, 4);
-    if (pp == 0) {
-      ib = (ib == m) ? 1 : ib + 1;
-    } else {
-      ia = (ia == m) ? 1 : ia + 1;
-      ib = (ib == m) ? 1 : ib + 1;
+  };
+  // Round r of the circle schedule pairs column 0 with column 1 + r and,
+  // for slot p = 1 .. P-1, column 1 + (p + r) mod m with 1 + (m - p + r) mod m.
+  if (P <= ngrp) {
+    // one slot per lane group: the positions advance by one each round
+    const int pp = grp;
+    int ia = (pp == 0) ? 0 : 1 + pp;
+    int ib = (pp == 0) ? 1 : 1 + m - pp;
+    const bool slot_ok = pp < P;
+    for (int r = 0; r < m; ++r) {
+      pair(ia, ib, slot_ok && ia < n && ib < n);
+      if (pp == 0) {
+        ib = (ib == m) ? 1 : ib + 1;
+      } else {
+        ia = (ia == m) ? 1 : ia + 1;
+        ib = (ib == m) ? 1 : ib + 1;
+      }
+      __syncthreads();
     }
-    __syncthreads();
+  } else {
+    // more pairs than lane groups: every group takes the slots grp,
+    // grp + ngrp, ... of each round in turn (the pairs of a round are
+    // disjoint, so their order does not matter)
+    const int nslot = (P + ngrp - 1) / ngrp;
+    for (int r = 0; r < m; ++r) {
+      for (int u = 0; u < nslot; ++u) {
+        const int pp = grp + u * ngrp;
+        const int ia = (pp == 0) ? 0 : 1 + (pp + r) % m;
+        const int ib = (pp == 0) ? 1 + r : 1 + (m - pp + r) % m;
+        pair(ia, ib, pp < P && ia < n && ib < n);
+      }
+      __syncthreads();
+    }
   }
   return rotated;
 }
@@ -616,7 +417,7 @@ __device__ __forceinline__ int jacobi_lds(Ctx& C, sc2* X, int len, int ncol, int
   };
   for (int sw = 0; sw < max_sweeps && n >= 2; ++sw) {
     const int P = (n + 1) >> 1;
-    // at most 8 rows per lane; the launch guarantees P * G <= NT for that
+    // at most 8 rows per lane (groups of up to 32 lanes for 256 rows)
     const int G = uniform(max(min(lanes_per(P, NT), pad), pad / 8));
     int rotated;
     long long tj = ph_now(C);
@@ -679,24 +480,42 @@ __device__ __forceinline__ int jacobi_lds(Ctx& C, sc2* X, int len, int ncol, int
 
 // Sort the n singular values (descending, ties by column index), choose the
 // kept count k by the truncation rule and compute 1/||sigma_{1..k}||.
-// n <= 64 (one wave decides).
+// n <= 256 (one wave decides, up to four values per lane).
 __device__ __forceinline__ void choose_k(Ctx& C, int n, int len, int capk) {
   if (C.tid < 64) {
-    const int c = C.tid;
-    double v = (c < n) ? C.sig[c] : -1.0;
-    if (!(v == v)) v = -1.0;
-    int rank = 0;
+    const int lane = C.tid;
+    double v[4];
+    int rk[4];
+    unsigned long long kk = 0ull;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      v[q] = -1.0;
+      rk[q] = 0;
+      if (q * 64 < n) {
+        const int c = lane + 64 * q;
+        double x = (c < n) ? C.sig[c] : -1.0;
+        if (!(x == x)) x = -1.0;
+        int rank = 0;
 #pragma unroll 4
-    for (int d = 0; d < n; ++d) {
-      double w = C.sig[d];
-      if (!(w == w)) w = -1.0;
-      rank += (w > v) || (w == v && d < c);
+        for (int d = 0; d < n; ++d) {
+          double w = C.sig[d];
+          if (!(w == w)) w = -1.0;
+          rank += (w > x) || (w == x && d < c);
+        }
+        if (c < n) {
+          C.perm[rank] = c;
+          kk = umax64(kk, argmax_key(x, c));
+        }
+        v[q] = x;
+        rk[q] = rank;
+      }
     }
-    if (c < n) C.perm[rank] = c;
-    const unsigned long long key = wave_max_u64(c < n ? argmax_key(v, c) : 0ull);
-    const double smax = (key != 0ull) ? C.sig[63 - (int)(key & 63ull)] : 0.0;
-    const unsigned long long ball = __ballot(c < n && v >= C.md.eps * smax);
-    int k = __popcll(ball);
+    const unsigned long long key = wave_max_u64(kk);
+    const double smax = (key != 0ull) ? C.sig[argmax_index(key)] : 0.0;
+    int k = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (q * 64 < n) k += __popcll(__ballot(lane + 64 * q < n && v[q] >= C.md.eps * smax));
     if (k > C.md.chi) k = C.md.chi;
     if (k < 1) k = 1;
     const int lim = len < n ? len : n;
@@ -706,8 +525,12 @@ __device__ __forceinline__ void choose_k(Ctx& C, int n, int len, int capk) {
       over = 1;
       k = capk;
     }
-    const double s2 = wave_sum((c < n && rank < k) ? v * v : 0.0);
-    if (c == 0) {
+    double part = 0.0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (lane + 64 * q < n && rk[q] < k) part += v[q] * v[q];
+    const double s2 = wave_sum(part);
+    if (lane == 0) {
       if (over) flag_or(C, 1);
       if (!(smax > 0.0) || !(s2 == s2)) flag_or(C, 4);
       C.sk[0] = k;
@@ -1047,4 +870,4 @@ __device__ __forceinline__ c2 left_envs(Ctx& C, const c2* bra, const int* bd, co
   return out;
 }
 
-}  // namespace tnrg
+}  // namespace TNRG_NS

@@ -13,7 +13,7 @@
 #include <string>
 
 #include "tnrg.h"
-#include "tnrg_device.hpp"
+#include "tnrg_common.hpp"
 
 using namespace tnrg;
 
@@ -83,232 +83,9 @@ __global__ void k_gates(int M, int N, double dt, const double* __restrict__ ux,
   }
 }
 
-// ============================================================================
-// Context set-up shared by the kernels.
-struct Shared {
-  Layout L;
-  int sdims[kMaxSites + 1];
-  double red[kMaxWaves * 8];
-  int sflag;
-  int sk;
-  double sinv;
-  double sd[4];
-  int si[4];
-  long long sstat[kStats];
-};
-
-__device__ __forceinline__ Ctx make_ctx(Shared& sh, c2* dyn, int cap, const ModelDev& md, c2* X0) {
-  Ctx C;
-  C.tid = threadIdx.x;
-  C.nt = blockDim.x;
-  C.cap = cap;
-  // buffers sized from P2 = max(4, pow2(2 cap)) so padded columns always fit
-  int P2 = 4;
-  while (P2 < 2 * cap) P2 <<= 1;
-  const int half = P2 * P2 / 2;
-  sc2* base = (sc2*)dyn;
-  C.LC = base;
-  C.LO = base + half;
-  C.X = base + 2 * half;
-  sdbl* d = (sdbl*)(C.X + P2 * (P2 + 1));
-  C.sig = d;
-  C.perm = (sint*)(d + P2);
-  C.X0 = X0;
-  C.L = (sLayout*)&sh.L;
-  C.sdims = (sint*)sh.sdims;
-  C.md = md;
-  C.sflag = (sint*)&sh.sflag;
-  C.sstat = (sll*)sh.sstat;
-  C.red = (sdbl*)sh.red;
-  C.sk = (sint*)&sh.sk;
-  C.sinv = (sdbl*)&sh.sinv;
-  C.sd = (sdbl*)sh.sd;
-  C.si = (sint*)sh.si;
-  if (C.tid == 0) {
-    sh.sflag = 0;
-    for (int q = 0; q < kStats; ++q) sh.sstat[q] = 0;
-  }
-  return C;
-}
-
-static size_t dyn_lds_bytes(int cap) {
-  size_t P2 = 4;
-  while (P2 < (size_t)2 * cap) P2 <<= 1;
-  return (P2 * P2 + P2 * (P2 + 1)) * sizeof(c2) + P2 * sizeof(double) + P2 * sizeof(int);
-}
 
 // ============================================================================
-// Boundary insertions (App. A): with the left environments of <b_{l+1}|a_l>
-// stored, sweep right to left; at each site form the transition matrix
-// rho_j[s][s'] = <b|(|s><s'|)_j|a> and, on bonds with a u^zz control, the
-// two-site element of (R Z R^dag) (x) (R Z R^dag); accumulate
-//   outer half of slice l   (l >= 1):    G = dR R^dag
-//   inner half of slice l+1 (l <= M-1):  G = R^dag dR
-//   ZZ control of slice l   (l >= 1):    -i dt <b|W_b W_{b+1}|a>
-// into the trajectory's gradient as 2 Re(conj(O) dO) (and dO itself when
-// requested).  lb is the 1-based boundary index l = 0..M.
-struct GradOut {
-  double* g;  // [nctrl] 2 Re(conj O dO)
-  c2* dO;     // [nctrl] or nullptr
-  c2 O;
-};
-
-__device__ __forceinline__ void right_insertions(Ctx& C, const c2* bra, const int* bd, const c2* ket,
-                                 const int* kd, const sLayout& L, const c2* envs, int lb,
-                                 const c2* gates, GradOut go) {
-  const int N = C.md.N, M = C.md.M;
-  const int cc = C.cap * C.cap;
-  const double dt = C.md.dt;
-  EnvBufs eb = env_bufs(C);
-  sc2* TF = eb.TF;
-  sc2* TFp = eb.TFp;
-  sc2* Tq = C.LO;  // two-site intermediate (2 cap^2)
-  if (C.tid == 0) eb.F[0] = cmk(1.0, 0.0);
-  __syncthreads();
-  for (int j = N - 1; j >= 0; --j) {
-    const int bl = bd[j], br = bd[j + 1], al = kd[j], ar = kd[j + 1];
-    const c2* A = ket + L.off[j];
-    const c2* Bt = bra + L.off[j];
-    const int rc = L.cap[j + 1];
-    for (int idx = C.tid; idx < bl * al; idx += C.nt) eb.E[idx] = envs[(size_t)j * cc + idx];
-    if (C.tid == 0) C.sstat[5] += 16LL * (al * br * ar + bl * br * al + al * bl * br);
-    // TF[s'][a][x] = sum_y A[a,s',y] F[y][x]     (al x br)
-    for (int idx = C.tid; idx < 2 * al * br; idx += C.nt) {
-      const int s = idx / (al * br);
-      const int rem = idx - s * al * br;
-      const int a = rem / br, x = rem - a * br;
-      c2 acc = cmk(0.0, 0.0);
-      for (int y = 0; y < ar; ++y) acc = cfma(A[(size_t)(a * 2 + s) * rc + y], eb.F[y * br + x], acc);
-      TF[s * cc + a * br + x] = acc;
-    }
-    __syncthreads();
-    // rho[s][s'] = sum_{z,x} conj(B[z,s,x]) sum_a E[z][a] TF[s'][a][x]
-    c2 rho[4] = {cmk(0, 0), cmk(0, 0), cmk(0, 0), cmk(0, 0)};
-    for (int idx = C.tid; idx < bl * br; idx += C.nt) {
-      const int z = idx / br, x = idx - z * br;
-      c2 u0 = cmk(0.0, 0.0), u1 = cmk(0.0, 0.0);
-      for (int a = 0; a < al; ++a) {
-        const c2 e = eb.E[z * al + a];
-        u0 = cfma(e, TF[a * br + x], u0);
-        u1 = cfma(e, TF[cc + a * br + x], u1);
-      }
-      const c2 b0 = Bt[(size_t)(z * 2 + 0) * rc + x];
-      const c2 b1 = Bt[(size_t)(z * 2 + 1) * rc + x];
-      rho[0] = cfmac(b0, u0, rho[0]);
-      rho[1] = cfmac(b0, u1, rho[1]);
-      rho[2] = cfmac(b1, u0, rho[2]);
-      rho[3] = cfmac(b1, u1, rho[3]);
-    }
-    block_sum<4>(C, rho);
-    // F_j[a][z] = sum_s sum_x TF[s][a][x] conj(B[z,s,x])   (al x bl)
-    for (int idx = C.tid; idx < al * bl; idx += C.nt) {
-      const int a = idx / bl, z = idx - a * bl;
-      c2 acc = cmk(0.0, 0.0);
-      for (int s = 0; s < 2; ++s)
-        for (int x = 0; x < br; ++x)
-          acc = cfmac(Bt[(size_t)(z * 2 + s) * rc + x], TF[s * cc + a * br + x], acc);
-      eb.F[idx] = acc;
-    }
-    // two-site element on a controlled bond j (needs site j+1 and TFp)
-    const bool zz = (lb >= 1) && (j <= N - 2) && bit(C.md.zzm, j);
-    c2 val = cmk(0.0, 0.0);
-    if (zz) {
-      const int s0 = lb - 1;
-      const M22 R1 = m22_load(gate_ptr(gates, N, s0, j));
-      const M22 R2 = m22_load(gate_ptr(gates, N, s0, j + 1));
-      M22 Zm;
-      Zm.m[0] = cmk(1, 0); Zm.m[1] = cmk(0, 0); Zm.m[2] = cmk(0, 0); Zm.m[3] = cmk(-1, 0);
-      const M22 W1 = m22_mul(m22_mul(R1, Zm), m22_dag(R1));
-      const M22 W2 = m22_mul(m22_mul(R2, Zm), m22_dag(R2));
-      // Tq[t][z][y] = sum_w E[z][w] A[w,t,y]      (bl x ar)
-      for (int idx = C.tid; idx < 2 * bl * ar; idx += C.nt) {
-        const int t = idx / (bl * ar);
-        const int rem = idx - t * bl * ar;
-        const int z = rem / ar, y = rem - z * ar;
-        c2 acc = cmk(0.0, 0.0);
-        for (int w = 0; w < al; ++w) acc = cfma(eb.E[z * al + w], A[(size_t)(w * 2 + t) * rc + y], acc);
-        Tq[t * cc + z * ar + y] = acc;
-      }
-      __syncthreads();
-      // E'[x][y] = sum_{s,t} W1[s][t] sum_z conj(B[z,s,x]) Tq[t][z][y]   (br x ar) -> E
-      for (int idx = C.tid; idx < br * ar; idx += C.nt) {
-        const int x = idx / ar, y = idx - x * ar;
-        c2 acc = cmk(0.0, 0.0);
-        for (int s = 0; s < 2; ++s) {
-          for (int t = 0; t < 2; ++t) {
-            c2 inner = cmk(0.0, 0.0);
-            for (int z = 0; z < bl; ++z)
-              inner = cfmac(Bt[(size_t)(z * 2 + s) * rc + x], Tq[t * cc + z * ar + y], inner);
-            acc = cfma(W1.m[2 * s + t], inner, acc);
-          }
-        }
-        eb.E[idx] = acc;
-      }
-      __syncthreads();
-      // rho'(s,t) on site j+1 with E' and TFp = A_{j+1} F_{j+2}
-      const int bl2 = br, br2 = bd[j + 2], al2 = ar;
-      const c2* B2 = bra + L.off[j + 1];
-      const int rc2 = L.cap[j + 2];
-      c2 rp[4] = {cmk(0, 0), cmk(0, 0), cmk(0, 0), cmk(0, 0)};
-      for (int idx = C.tid; idx < bl2 * br2; idx += C.nt) {
-        const int z = idx / br2, x = idx - z * br2;
-        c2 u0 = cmk(0.0, 0.0), u1 = cmk(0.0, 0.0);
-        for (int a = 0; a < al2; ++a) {
-          const c2 e = eb.E[z * al2 + a];
-          u0 = cfma(e, TFp[a * br2 + x], u0);
-          u1 = cfma(e, TFp[cc + a * br2 + x], u1);
-        }
-        const c2 b0 = B2[(size_t)(z * 2 + 0) * rc2 + x];
-        const c2 b1 = B2[(size_t)(z * 2 + 1) * rc2 + x];
-        rp[0] = cfmac(b0, u0, rp[0]);
-        rp[1] = cfmac(b0, u1, rp[1]);
-        rp[2] = cfmac(b1, u0, rp[2]);
-        rp[3] = cfmac(b1, u1, rp[3]);
-      }
-      block_sum<4>(C, rp);
-      for (int q = 0; q < 4; ++q) val = cfma(W2.m[q], rp[q], val);
-    }
-    if (C.tid == 0) {
-      auto tr = [&](const M22& G) {
-        c2 v = cmk(0.0, 0.0);
-        for (int q = 0; q < 4; ++q) v = cfma(G.m[q], rho[q], v);
-        return v;
-      };
-      auto add = [&](size_t idx, c2 v) {
-        go.g[idx] += 2.0 * (go.O.x * v.x + go.O.y * v.y);
-        if (go.dO) go.dO[idx] = cadd(go.dO[idx], v);
-      };
-      const size_t MN = (size_t)M * N;
-      if (lb >= 1) {
-        const int s0 = lb - 1;
-        const c2* gp = gate_ptr(gates, N, s0, j);
-        const M22 R = m22_load(gp), dx = m22_load(gp + 4), dy = m22_load(gp + 8);
-        const M22 Rd = m22_dag(R);
-        add((size_t)s0 * N + j, tr(m22_mul(dx, Rd)));
-        add(MN + (size_t)s0 * N + j, tr(m22_mul(dy, Rd)));
-      }
-      if (lb <= M - 1) {
-        const int s0 = lb;
-        const c2* gp = gate_ptr(gates, N, s0, j);
-        const M22 R = m22_load(gp), dx = m22_load(gp + 4), dy = m22_load(gp + 8);
-        const M22 Rd = m22_dag(R);
-        add((size_t)s0 * N + j, tr(m22_mul(Rd, dx)));
-        add(MN + (size_t)s0 * N + j, tr(m22_mul(Rd, dy)));
-      }
-      if (zz) {
-        const int s0 = lb - 1;
-        // -i dt val
-        add(2 * MN + (size_t)s0 * (N - 1) + j, cmk(dt * val.y, -dt * val.x));
-      }
-    }
-    __syncthreads();
-    sc2* tmp = TF;
-    TF = TFp;
-    TFp = tmp;
-  }
-}
-
-// ============================================================================
+// Kernel arguments (shared by both memory-space variants).
 // Persistent fidelity+gradient kernel: one workgroup per trajectory (k, r).
 struct GrapeArgs {
   ModelDev md;
@@ -331,136 +108,55 @@ struct GrapeArgs {
   long long* stats;
   char* traj_base;
   size_t traj_bytes, slot_bytes, dims_off, off_x0, off_env, off_O, off_g;
+  size_t off_big;  // working buffers of the global-scratch variant (capacities above 32)
   c2* overlaps;
   c2* traj_dO;
   int mode;                // kModeForward | kModeBackward
   unsigned long long tag;  // fingerprint of the call's arguments
 };
 
+
 constexpr int kModeForward = 1, kModeBackward = 2;
 
-// Adjoint sweep of one trajectory (App. A): insertions at boundary M with the
-// environments `envs` already built for <T|a_M>, then for l = M-1 .. 0 the
-// backward state b_{l+1} = U_{l+1}^dag b_{l+2} and the insertions at the
-// boundary pair (b_{l+1}, a_l), the a_l recomputed segment by segment from
-// the checkpoints a_0, a_cs, a_2cs, ...
-__device__ __forceinline__ void grape_adjoint(Ctx& C, const GrapeArgs& A, char* base, GradOut& go,
-                                              c2* envs, const double* Jrow, const sLayout& L) {
-  const int M = A.md.M;
-  auto slot = [&](int s) { return reinterpret_cast<c2*>(base + (size_t)s * A.slot_bytes); };
-  auto sdim = [&](int s) {
-    return reinterpret_cast<int*>(base + (size_t)s * A.slot_bytes + A.dims_off);
-  };
-  const int s_seg = A.nck, s_aM = A.nck + A.cs - 1, s_b = A.nck + A.cs + 1;
-  long long te = ph_now(C);
-  right_insertions(C, slot(s_b), sdim(s_b), slot(s_aM), sdim(s_aM), L, envs, M, A.gates, go);
-  ph_add(C, kPhEnvR, te);
-  adjoint_slice(C, slot(s_b), sdim(s_b), slot(s_b), sdim(s_b), A.gates, M - 1, A.uzz, Jrow);
-  for (int i = A.nck - 1; i >= 0; --i) {
-    const int L0 = i * A.cs;
-    const int L1 = min((i + 1) * A.cs, M) - 1;
-    for (int l = L0 + 1; l <= L1; ++l) {
-      const int src = (l - 1 == L0) ? i : s_seg + (l - 2 - L0);
-      const int dst = s_seg + (l - 1 - L0);
-      forward_slice(C, slot(src), sdim(src), slot(dst), sdim(dst), A.gates, l - 1, A.uzz, Jrow);
-    }
-    for (int l = L1; l >= L0; --l) {
-      const int ket = (l == L0) ? i : s_seg + (l - 1 - L0);
-      te = ph_now(C);
-      left_envs(C, slot(s_b), sdim(s_b), L, slot(ket), sdim(ket), L, envs);
-      ph_add(C, kPhEnvL, te);
-      right_insertions(C, slot(s_b), sdim(s_b), slot(ket), sdim(ket), L, envs, l, A.gates, go);
-      ph_add(C, kPhEnvR, te);
-      if (l >= 1)
-        adjoint_slice(C, slot(s_b), sdim(s_b), slot(s_b), sdim(s_b), A.gates, l - 1, A.uzz, Jrow);
-    }
-  }
-}
 
-__global__ void __launch_bounds__(256) k_grape(GrapeArgs A) {
-  extern __shared__ __align__(16) c2 dyn[];
-  __shared__ Shared sh;
-  const int t = blockIdx.x;
-  const int k = t / A.R, r = t % A.R;
-  const int N = A.md.N, M = A.md.M;
-  char* base = A.traj_base + (size_t)t * A.traj_bytes;
-  Ctx C = make_ctx(sh, dyn, A.dcap, A.md, reinterpret_cast<c2*>(base + A.off_x0));
-  layout_build(*(sLayout*)&sh.L, N, A.dcap);
-  const sLayout& L = *(sLayout*)&sh.L;
-  long long t_all = ph_now(C);
-  auto slot = [&](int s) { return reinterpret_cast<c2*>(base + (size_t)s * A.slot_bytes); };
-  auto sdim = [&](int s) {
-    return reinterpret_cast<int*>(base + (size_t)s * A.slot_bytes + A.dims_off);
-  };
-  const int s_seg = A.nck, s_aM = A.nck + A.cs - 1, s_work = A.nck + A.cs, s_b = A.nck + A.cs + 1;
-  const double* Jrow = A.J + (size_t)k * (N - 1);
-  c2* envs = reinterpret_cast<c2*>(base + A.off_env);
-  double* g = reinterpret_cast<double*>(base + A.off_g);
-  c2* dO = A.traj_dO ? A.traj_dO + (size_t)t * A.nctrl : nullptr;
-  const bool fwd = A.mode & kModeForward, bwd = A.mode & kModeBackward;
-  unsigned long long* tagp = reinterpret_cast<unsigned long long*>(base + A.off_O + sizeof(c2));
+// mps_evolve kernel: one workgroup per trajectory, slices in place.
+struct EvolveArgs {
+  ModelDev md;
+  const double* uzz;
+  const double* J;
+  const c2* gates;
+  c2* data;
+  int* dims;
+  int dcap;
+  long long stride;
+  int l_begin, l_end, adjoint;
+  c2* x0;
+  c2* big;  // working buffers of the global-scratch variant, big_stride per trajectory
+  size_t big_stride;
+  int* flags;
+  long long* stats;
+};
 
-  if (!fwd) {
-    // the adjoint sweep reads the checkpoints a forward call with the same
-    // arguments left in this workspace; it also keeps that call's flags and
-    // counters and adds its own
-    if (C.tid == 0) {
-      if (*tagp == A.tag) {
-        sh.sflag = A.flags[t] & ~TNRG_FLAG_STALE;
-        for (int q = 0; q < kStats; ++q) sh.sstat[q] = A.stats[(size_t)t * kStats + q];
-      } else {
-        sh.sflag = TNRG_FLAG_STALE;
-      }
-    }
-  }
-  if (bwd) {
-    for (int i = C.tid; i < A.nctrl; i += C.nt) {
-      g[i] = 0.0;
-      if (dO) dO[i] = cmk(0.0, 0.0);
-    }
-  }
-  __syncthreads();
-  if (!(sh.sflag & TNRG_FLAG_STALE)) {
-    copy_mps(C, A.tg_data + (size_t)r * A.tg_stride, A.tg_dims + (size_t)r * (N + 1), A.tg_dcap,
-             slot(s_b), sdim(s_b), L);
-    if (fwd) {
-      copy_mps(C, A.in_data + (size_t)r * A.in_stride, A.in_dims + (size_t)r * (N + 1),
-               A.in_dcap, slot(0), sdim(0), L);
-      // forward pass with checkpoints a_0, a_cs, a_2cs, ...
-      int cur = 0;
-      for (int l = 0; l < M; ++l) {
-        int dst;
-        if (l + 1 == M)
-          dst = s_aM;
-        else if ((l + 1) % A.cs == 0)
-          dst = (l + 1) / A.cs;
-        else
-          dst = s_work;
-        forward_slice(C, slot(cur), sdim(cur), slot(dst), sdim(dst), A.gates, l, A.uzz, Jrow);
-        cur = dst;
-      }
-    }
-    // boundary M: O = <T|a_M> (recomputed bit for bit by a backward-only call)
-    GradOut go;
-    go.g = g;
-    go.dO = dO;
-    long long te = ph_now(C);
-    go.O = left_envs(C, slot(s_b), sdim(s_b), L, slot(s_aM), sdim(s_aM), L, envs);
-    ph_add(C, kPhEnvL, te);
-    if (fwd && C.tid == 0) {
-      *reinterpret_cast<c2*>(base + A.off_O) = go.O;
-      *tagp = A.tag;
-      if (A.overlaps) A.overlaps[t] = go.O;
-    }
-    if (bwd) grape_adjoint(C, A, base, go, envs, Jrow, L);
-  }
-  __syncthreads();
-  ph_add(C, kPhTotal, t_all);
-  if (C.tid == 0) {
-    A.flags[t] = sh.sflag;
-    for (int q = 0; q < kStats; ++q) A.stats[(size_t)t * kStats + q] = sh.sstat[q];
-  }
-}
+
+// mps_overlap kernel: out[t] = <bra_{t % nb} | ket_t>.
+struct OverlapArgs {
+  ModelDev md;
+  const c2* bra;
+  const int* bdims;
+  int bdcap;
+  long long bstride;
+  int nb;
+  const c2* ket;
+  const int* kdims;
+  int kdcap;
+  long long kstride;
+  int cap;
+  c2* out;
+  int* flags;
+  c2* big;
+  size_t big_stride;
+};
+
 
 // Deterministic ensemble reduction: F = mean |O_t|^2, grad = mean of the
 // per-trajectory 2 Re(conj O dO) (Sec. II, Eq. 7), summed in trajectory order.
@@ -491,89 +187,33 @@ __global__ void k_reduce(int n_traj, int nctrl, int MN, int MN1, const char* tra
   }
 }
 
-// ============================================================================
-// mps_evolve kernel: one workgroup per trajectory, slices in place.
-struct EvolveArgs {
-  ModelDev md;
-  const double* uzz;
-  const double* J;
-  const c2* gates;
-  c2* data;
-  int* dims;
-  int dcap;
-  long long stride;
-  int l_begin, l_end, adjoint;
-  c2* x0;
-  int* flags;
-  long long* stats;
-};
 
-__global__ void __launch_bounds__(256) k_evolve(EvolveArgs A) {
-  extern __shared__ __align__(16) c2 dyn[];
-  __shared__ Shared sh;
-  const int t = blockIdx.x;
-  const int N = A.md.N;
-  const int cap = A.dcap;
-  Ctx C = make_ctx(sh, dyn, cap, A.md, A.x0 + (size_t)t * x_elems(cap));
-  layout_build(*(sLayout*)&sh.L, N, cap);
-  c2* psi = A.data + (size_t)t * A.stride;
-  int* d = A.dims + (size_t)t * (N + 1);
-  const double* Jrow = A.J + (size_t)t * (N - 1);
-  for (int b = C.tid; b <= N; b += C.nt) {
-    const int db = d[b];
-    if (db > sh.L.cap[b] || db < 1 || ((b == 0 || b == N) && db != 1)) flag_or(C, 1);
-  }
-  __syncthreads();
-  if (!sh.sflag) {
-    if (!A.adjoint) {
-      for (int l = A.l_begin; l < A.l_end; ++l) forward_slice(C, psi, d, psi, d, A.gates, l, A.uzz, Jrow);
-    } else {
-      for (int l = A.l_end - 1; l >= A.l_begin; --l)
-        adjoint_slice(C, psi, d, psi, d, A.gates, l, A.uzz, Jrow);
-    }
-  }
-  __syncthreads();
-  if (C.tid == 0) {
-    A.flags[t] = sh.sflag;
-    for (int q = 0; q < kStats; ++q) A.stats[(size_t)t * kStats + q] = sh.sstat[q];
-  }
+// The two variants of the persistent kernels.
+#define TNRG_NS lds
+#define TNRG_AS __attribute__((address_space(3)))
+#define TNRG_BIG 0
+#include "tnrg_device.hpp"
+#include "tnrg_kernels.inc"
+#undef TNRG_NS
+#undef TNRG_AS
+#undef TNRG_BIG
+#define TNRG_NS big
+#define TNRG_AS
+#define TNRG_BIG 1
+#include "tnrg_device.hpp"
+#include "tnrg_kernels.inc"
+#undef TNRG_NS
+#undef TNRG_AS
+#undef TNRG_BIG
+
+// Working buffers of one workgroup for capacity cap (LDS in the first
+// variant, global scratch in the second).
+static size_t dyn_lds_bytes(int cap) {
+  size_t P2 = 4;
+  while (P2 < (size_t)2 * cap) P2 <<= 1;
+  return (P2 * P2 + P2 * (P2 + 1)) * sizeof(c2) + P2 * sizeof(double) + P2 * sizeof(int);
 }
 
-// mps_overlap kernel: out[t] = <bra_{t % nb} | ket_t>.
-struct OverlapArgs {
-  ModelDev md;
-  const c2* bra;
-  const int* bdims;
-  int bdcap;
-  long long bstride;
-  int nb;
-  const c2* ket;
-  const int* kdims;
-  int kdcap;
-  long long kstride;
-  int cap;
-  c2* out;
-  int* flags;
-};
-
-__global__ void __launch_bounds__(256) k_overlap(OverlapArgs A) {
-  extern __shared__ __align__(16) c2 dyn[];
-  __shared__ Shared sh;
-  __shared__ Layout L2;
-  const int t = blockIdx.x;
-  const int N = A.md.N;
-  Ctx C = make_ctx(sh, dyn, A.cap, A.md, nullptr);
-  layout_build(*(sLayout*)&sh.L, N, A.kdcap);
-  layout_build(*(sLayout*)&L2, N, A.bdcap);
-  const int rb = t % A.nb;
-  const c2 o = left_envs(C, A.bra + (size_t)rb * A.bstride, A.bdims + (size_t)rb * (N + 1), *(sLayout*)&L2,
-                         A.ket + (size_t)t * A.kstride, A.kdims + (size_t)t * (N + 1), *(sLayout*)&sh.L,
-                         nullptr);
-  if (C.tid == 0) {
-    A.out[t] = o;
-    A.flags[t] = 0;
-  }
-}
 
 // ============================================================================
 // Host side: validation, workspace layout, launches.
@@ -594,6 +234,16 @@ int fail(int code, const char* fmt, ...) {
 int hip_fail(hipError_t e, const char* what) {
   return fail(TNRG_EHIP, "%s: %s", what, hipGetErrorString(e));
 }
+
+}  // namespace
+
+// Shared with the serving runtime (tnrg_server.cpp); not exported.
+__attribute__((visibility("hidden"))) int tnrg_set_error(int code, const char* msg) {
+  g_err = msg;
+  return code;
+}
+
+namespace {
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -640,36 +290,39 @@ int check_batch(const tnrg_mps_batch* b, int N, const char* name) {
 // overrides this per capacity.
 std::atomic<int> g_plan_threads[kMaxSites + 1];
 
-// Fewest threads for capacity cap: every Jacobi round processes up to cap
-// column pairs with at least pow2(2 cap) / 8 lanes each (8 rows per lane).
-int min_threads(int cap) {
+// Default threads for capacity cap: enough that one Jacobi round processes
+// all of its up to cap column pairs at once with pow2(2 cap) / 8 lanes each
+// (8 rows per lane), at most 256.  Fewer threads loop over the pairs.
+int default_threads(int cap) {
   int p2 = 1;
   while (p2 < 2 * cap) p2 <<= 1;
   const int need = (p2 / 8 > 1 ? p2 / 8 : 1) * cap;
   int nt = 64;
-  while (nt < need) nt *= 2;
+  while (nt < need && nt < 256) nt *= 2;
   return nt;
 }
-
-int default_threads(int cap) { return min_threads(cap); }
 
 int threads_for_cap(int cap) {
   if (cap >= 0 && cap <= kMaxSites) {
     const int t = g_plan_threads[cap].load(std::memory_order_relaxed);
-    if (t >= min_threads(cap)) return t;
+    if (t >= 64) return t;
   }
   return default_threads(cap);
 }
 
 // Largest dynamic LDS a workgroup may use on gfx950.
-constexpr size_t kMaxDynLds = 160 * 1024 - sizeof(Shared) - 512;
-// The bond update keeps a (2 cap) x (2 cap) problem inside one wave's lane
-// range for its pivot search and sort.
-constexpr int kMaxCap = 32;
+constexpr size_t kMaxDynLds = 160 * 1024 - sizeof(lds::Shared) - 512;
+// Capacities up to kMaxLdsCap keep the working buffers in LDS; larger ones
+// (up to kMaxCap: a 2 cap x 2 cap bond problem of at most 256 columns for the
+// wave-level pivot search and sort) in per-trajectory global scratch.
+constexpr int kMaxLdsCap = 32;
+constexpr int kMaxCap = 128;
+bool use_lds(int cap) { return cap <= kMaxLdsCap && dyn_lds_bytes(cap) <= kMaxDynLds; }
+size_t big_bytes(int cap) { return use_lds(cap) ? 0 : align256(dyn_lds_bytes(cap)); }
 
 struct GrapeLayout {
   int cs, nck, nslots, nctrl, dcap;
-  size_t slot_bytes, dims_off, off_x0, off_env, off_O, off_g, traj_bytes;
+  size_t slot_bytes, dims_off, off_x0, off_env, off_O, off_g, off_big, traj_bytes;
   size_t off_flags, off_stats, off_gates, off_traj, total;
 };
 
@@ -688,7 +341,8 @@ GrapeLayout grape_layout(const tnrg_model* md, int K, int R, int dcap, int cs) {
   g.off_env = g.off_x0 + align256((size_t)x_elems(dcap) * sizeof(c2));
   g.off_O = g.off_env + align256((size_t)(N + 1) * dcap * dcap * sizeof(c2));
   g.off_g = g.off_O + 256;
-  g.traj_bytes = align256(g.off_g + (size_t)g.nctrl * sizeof(double));
+  g.off_big = align256(g.off_g + (size_t)g.nctrl * sizeof(double));
+  g.traj_bytes = g.off_big + big_bytes(dcap);
   const int nt = K * R;
   g.off_flags = 0;
   g.off_stats = align256((size_t)nt * sizeof(int));
@@ -753,7 +407,7 @@ size_t mps_evolve_workspace_bytes(const tnrg_model* md, int32_t n_traj, int32_t 
   const size_t nt = (size_t)n_traj;
   return align256(nt * sizeof(int)) + align256(nt * kStats * sizeof(long long)) +
          align256((size_t)md->m * md->n * 12 * sizeof(c2)) +
-         nt * (size_t)x_elems(dcap) * sizeof(c2);
+         align256(nt * (size_t)x_elems(dcap) * sizeof(c2)) + nt * big_bytes(dcap);
 }
 
 int mps_evolve(const tnrg_model* md, const double* ux, const double* uy, const double* uzz,
@@ -768,9 +422,10 @@ int mps_evolve(const tnrg_model* md, const double* ux, const double* uy, const d
     return fail(TNRG_EINVAL, "slice range [%d, %d) outside [0, %d)", l_begin, l_end, md->m);
   const size_t need = mps_evolve_workspace_bytes(md, psi->n_traj, psi->dcap);
   if (ws_bytes < need) return fail(TNRG_ENOMEM, "workspace %zu < %zu bytes", ws_bytes, need);
-  const size_t lds = dyn_lds_bytes(psi->dcap);
-  if (lds > kMaxDynLds || psi->dcap > kMaxCap)
+  if (psi->dcap > kMaxCap)
     return fail(TNRG_EUNSUPPORTED, "dcap = %d is above the supported %d", psi->dcap, kMaxCap);
+  const bool in_lds = use_lds(psi->dcap);
+  const size_t lds = in_lds ? dyn_lds_bytes(psi->dcap) : 0;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   char* w = static_cast<char*>(ws);
   const size_t nt = psi->n_traj;
@@ -784,6 +439,9 @@ int mps_evolve(const tnrg_model* md, const double* ux, const double* uy, const d
   A.gates = gates;
   A.x0 = reinterpret_cast<c2*>(reinterpret_cast<char*>(gates) +
                                align256((size_t)md->m * md->n * 12 * sizeof(c2)));
+  A.big = reinterpret_cast<c2*>(reinterpret_cast<char*>(A.x0) +
+                                align256(nt * (size_t)x_elems(psi->dcap) * sizeof(c2)));
+  A.big_stride = big_bytes(psi->dcap) / sizeof(c2);
   A.data = reinterpret_cast<c2*>(psi->data);
   A.dims = psi->bond_dim;
   A.dcap = psi->dcap;
@@ -792,10 +450,14 @@ int mps_evolve(const tnrg_model* md, const double* ux, const double* uy, const d
   A.l_end = l_end;
   A.adjoint = adjoint ? 1 : 0;
   launch_gates(md, ux, uy, gates, s);
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_evolve),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  const void* kern = in_lds ? reinterpret_cast<const void*>(lds::k_evolve)
+                            : reinterpret_cast<const void*>(big::k_evolve);
+  hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute(k_evolve)");
-  hipLaunchKernelGGL(k_evolve, dim3(psi->n_traj), dim3(threads_for_cap(psi->dcap)), lds, s, A);
+  if (in_lds)
+    hipLaunchKernelGGL(lds::k_evolve, dim3(psi->n_traj), dim3(threads_for_cap(psi->dcap)), lds, s, A);
+  else
+    hipLaunchKernelGGL(big::k_evolve, dim3(psi->n_traj), dim3(threads_for_cap(psi->dcap)), 0, s, A);
   e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "k_evolve launch");
   return TNRG_OK;
@@ -803,9 +465,9 @@ int mps_evolve(const tnrg_model* md, const double* ux, const double* uy, const d
 
 size_t mps_overlap_workspace_bytes(int32_t n_traj, int32_t n_sites, int32_t dcap) {
   (void)n_sites;
-  (void)dcap;
-  if (n_traj < 1) return 0;
-  return align256((size_t)n_traj * sizeof(int)) + align256((size_t)n_traj * kStats * sizeof(long long));
+  if (n_traj < 1 || dcap < 1) return 0;
+  return align256((size_t)n_traj * sizeof(int)) + align256((size_t)n_traj * kStats * sizeof(long long)) +
+         (size_t)n_traj * big_bytes(dcap);
 }
 
 int mps_overlap(const tnrg_mps_batch* bra, const tnrg_mps_batch* ket, tnrg_c128* out, void* ws,
@@ -818,11 +480,12 @@ int mps_overlap(const tnrg_mps_batch* bra, const tnrg_mps_batch* ket, tnrg_c128*
   if ((rc = check_batch(ket, N, "ket"))) return rc;
   if (ket->n_traj % bra->n_traj) return fail(TNRG_EINVAL, "bra count must divide ket count");
   if (!out || !ws) return fail(TNRG_EINVAL, "NULL output/workspace");
-  const size_t need = mps_overlap_workspace_bytes(ket->n_traj, N, ket->dcap);
-  if (ws_bytes < need) return fail(TNRG_ENOMEM, "workspace %zu < %zu bytes", ws_bytes, need);
   const int cap = std::max(bra->dcap, ket->dcap);
-  const size_t lds = dyn_lds_bytes(cap);
-  if (lds > kMaxDynLds) return fail(TNRG_EUNSUPPORTED, "dcap = %d needs %zu bytes of LDS", cap, lds);
+  if (cap > kMaxCap) return fail(TNRG_EUNSUPPORTED, "dcap = %d is above the supported %d", cap, kMaxCap);
+  const size_t need = mps_overlap_workspace_bytes(ket->n_traj, N, cap);
+  if (ws_bytes < need) return fail(TNRG_ENOMEM, "workspace %zu < %zu bytes", ws_bytes, need);
+  const bool in_lds = use_lds(cap);
+  const size_t lds = in_lds ? dyn_lds_bytes(cap) : 0;
   OverlapArgs A;
   memset(&A, 0, sizeof A);
   A.md.N = N;
@@ -838,11 +501,18 @@ int mps_overlap(const tnrg_mps_batch* bra, const tnrg_mps_batch* ket, tnrg_c128*
   A.cap = cap;
   A.out = reinterpret_cast<c2*>(out);
   A.flags = static_cast<int*>(ws);
+  A.big = reinterpret_cast<c2*>(static_cast<char*>(ws) + align256((size_t)ket->n_traj * sizeof(int)) +
+                                align256((size_t)ket->n_traj * kStats * sizeof(long long)));
+  A.big_stride = big_bytes(cap) / sizeof(c2);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_overlap),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  const void* kern = in_lds ? reinterpret_cast<const void*>(lds::k_overlap)
+                            : reinterpret_cast<const void*>(big::k_overlap);
+  hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute(k_overlap)");
-  hipLaunchKernelGGL(k_overlap, dim3(ket->n_traj), dim3(threads_for_cap(cap)), lds, s, A);
+  if (in_lds)
+    hipLaunchKernelGGL(lds::k_overlap, dim3(ket->n_traj), dim3(threads_for_cap(cap)), lds, s, A);
+  else
+    hipLaunchKernelGGL(big::k_overlap, dim3(ket->n_traj), dim3(threads_for_cap(cap)), 0, s, A);
   e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "k_overlap launch");
   return TNRG_OK;
@@ -896,9 +566,10 @@ int grape_launch(int mode, const tnrg_model* md, const double* ux, const double*
                                  : (int)ceil(sqrt((double)md->m));
   const GrapeLayout G = grape_layout(md, K, R, cap, cs);
   if (ws_bytes < G.total) return fail(TNRG_ENOMEM, "workspace %zu < %zu bytes", ws_bytes, G.total);
-  const size_t lds = dyn_lds_bytes(cap);
-  if (lds > kMaxDynLds || cap > kMaxCap)
+  if (cap > kMaxCap)
     return fail(TNRG_EUNSUPPORTED, "dcap = %d is above the supported %d", cap, kMaxCap);
+  const bool in_lds = use_lds(cap);
+  const size_t lds = in_lds ? dyn_lds_bytes(cap) : 0;
   if ((long long)K * R > 0x7fffffff) return fail(TNRG_EINVAL, "too many trajectories");
 
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
@@ -937,6 +608,7 @@ int grape_launch(int mode, const tnrg_model* md, const double* ux, const double*
   A.off_env = G.off_env;
   A.off_O = G.off_O;
   A.off_g = G.off_g;
+  A.off_big = G.off_big;
   A.overlaps = reinterpret_cast<c2*>(overlaps);
   A.traj_dO = reinterpret_cast<c2*>(traj_dO);
   A.mode = mode;
@@ -951,10 +623,14 @@ int grape_launch(int mode, const tnrg_model* md, const double* ux, const double*
   }
 
   if (mode & kModeForward) launch_gates(md, ux, uy, gates, s);
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_grape),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  const void* kern = in_lds ? reinterpret_cast<const void*>(lds::k_grape)
+                            : reinterpret_cast<const void*>(big::k_grape);
+  hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute(k_grape)");
-  hipLaunchKernelGGL(k_grape, dim3(K * R), dim3(threads_for_cap(cap)), lds, s, A);
+  if (in_lds)
+    hipLaunchKernelGGL(lds::k_grape, dim3(K * R), dim3(threads_for_cap(cap)), lds, s, A);
+  else
+    hipLaunchKernelGGL(big::k_grape, dim3(K * R), dim3(threads_for_cap(cap)), 0, s, A);
   e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "k_grape launch");
   const int MN = md->m * md->n;

@@ -61,10 +61,36 @@ class _Batch(ctypes.Structure):
                 ("data", ctypes.c_void_p)]
 
 
+class _Request(ctypes.Structure):
+    _fields_ = [("md", ctypes.POINTER(_Model)), ("ux", ctypes.c_void_p),
+                ("uy", ctypes.c_void_p), ("uzz", ctypes.c_void_p), ("K", ctypes.c_int32),
+                ("J", ctypes.c_void_p), ("R", ctypes.c_int32),
+                ("inputs", ctypes.POINTER(_Batch)), ("targets", ctypes.POINTER(_Batch)),
+                ("dcap", ctypes.c_int32), ("F", ctypes.c_void_p), ("g_ux", ctypes.c_void_p),
+                ("g_uy", ctypes.c_void_p), ("g_uzz", ctypes.c_void_p),
+                ("overlaps", ctypes.c_void_p)]
+
+
+class _Completion(ctypes.Structure):
+    _fields_ = [("ticket", ctypes.c_int64), ("status", ctypes.c_int32),
+                ("dcap", ctypes.c_int32), ("launches", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("queue_ms", ctypes.c_double),
+                ("total_ms", ctypes.c_double)]
+
+
+class _ServerInfo(ctypes.Structure):
+    _fields_ = [("queued", ctypes.c_int32), ("running", ctypes.c_int32),
+                ("submitted", ctypes.c_int64), ("admitted", ctypes.c_int64),
+                ("completed", ctypes.c_int64), ("regrown", ctypes.c_int64),
+                ("cancelled", ctypes.c_int64), ("arena_bytes", ctypes.c_size_t),
+                ("arena_free", ctypes.c_size_t), ("arena_largest_free", ctypes.c_size_t)]
+
+
 _vp, _i32, _i64, _sz, _dp = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64,
                              ctypes.c_size_t, ctypes.c_void_p)
 _MP = ctypes.POINTER(_Model)
 _BP = ctypes.POINTER(_Batch)
+_SP = ctypes.c_void_p  # tnrg_server*
 
 _SIGS = {
     "tnrg_bond_cap": (_i32, [_i32, _i32, _i32]),
@@ -84,6 +110,15 @@ _SIGS = {
                                       _i32, _dp, _dp, _dp, _vp, _vp, _sz, _vp]),
     "tnrg_status": (ctypes.c_int, [_vp, _i32, ctypes.POINTER(ctypes.c_int32),
                                    ctypes.POINTER(ctypes.c_int64), _vp]),
+    "tnrg_server_create": (ctypes.c_int, [_vp, _sz, _i32, _i32, ctypes.POINTER(_SP)]),
+    "tnrg_server_submit": (ctypes.c_int, [_SP, ctypes.POINTER(_Request),
+                                          ctypes.POINTER(ctypes.c_int64)]),
+    "tnrg_server_progress": (ctypes.c_int, [_SP, ctypes.POINTER(_Completion), _i32,
+                                            ctypes.POINTER(ctypes.c_int32)]),
+    "tnrg_server_cancel_queued": (ctypes.c_int, [_SP, ctypes.POINTER(ctypes.c_int64), _i32,
+                                                 ctypes.POINTER(ctypes.c_int32)]),
+    "tnrg_server_info_get": (ctypes.c_int, [_SP, ctypes.POINTER(_ServerInfo)]),
+    "tnrg_server_destroy": (ctypes.c_int, [_SP]),
     "tnrg_plan_set_threads": (ctypes.c_int, [_i32, _i32]),
     "tnrg_plan_threads": (_i32, [_i32]),
     "tnrg_last_error": (ctypes.c_char_p, []),
@@ -278,7 +313,8 @@ def mps_evolve(model: Model, ux, uy, uzz, J, psi: MPSBatch, l_begin=0, l_end=Non
 def mps_overlap(bra: MPSBatch, ket: MPSBatch, stream=None) -> torch.Tensor:
     dev = ket.data.device
     out = torch.empty(ket.n_traj, dtype=torch.complex128, device=dev)
-    ws = _workspace(_lib.mps_overlap_workspace_bytes(ket.n_traj, ket.N, ket.dcap), dev)
+    ws = _workspace(_lib.mps_overlap_workspace_bytes(ket.n_traj, ket.N,
+                                                     max(ket.dcap, bra.dcap)), dev)
     b, k = bra.c(), ket.c()
     _check(_lib.mps_overlap(ctypes.byref(b), ctypes.byref(k), _ptr(out), _ptr(ws),
                             ws.numel(), _stream(stream)))
@@ -287,7 +323,9 @@ def mps_overlap(bra: MPSBatch, ket: MPSBatch, stream=None) -> torch.Tensor:
 
 # Capacity buckets tried in order when a bond outgrows the current one; the
 # last working bucket per problem shape is remembered (the chi-bucket plan).
-BUCKETS = (4, 8, 16, 32)
+# Buckets up to 32 keep the working buffers in LDS, 64 and 128 in global
+# scratch.
+BUCKETS = (4, 8, 16, 32, 64, 128)
 _plan_cache = {}
 
 

@@ -164,3 +164,47 @@ def test_degenerate_cut_compares_what_is_unique(P):
     for name in ("g_ux", "g_uy", "g_uzz"):
         g = res[name].cpu().numpy()
         assert np.all(np.isfinite(g)) and np.max(np.abs(g)) < 10.0
+
+
+# Capacities above 32 keep the bond-update working buffers in global scratch
+# instead of LDS (a second compilation of the same kernels).
+def test_global_scratch_variant_is_bitwise_the_lds_variant(P):
+    p = W.make_problem(task="cnot", N=8, M=9, T=2.7, chi=64, K=2, R=2, sigma=0.3, seed=51)
+    say("lds vs global-scratch variant: cnot N=8 (dims <= 16) at dcap 16, 64 and 128")
+    lib = P.tnrg._lib
+    try:
+        for c in (16, 64, 128):
+            assert lib.tnrg_plan_set_threads(c, 256) == 0
+        a = _grape_case(P, p, dcap=16)
+        b = _grape_case(P, p, dcap=64)
+        c = _grape_case(P, p, dcap=128)
+    finally:
+        for cap in (16, 64, 128):
+            lib.tnrg_plan_set_threads(cap, 0)
+    assert (a["dcap"], b["dcap"], c["dcap"]) == (16, 64, 128)
+    for name in ("F", "g_ux", "g_uy", "g_uzz", "overlaps", "traj_dO"):
+        assert torch.equal(a[name], b[name]), name
+        assert torch.equal(a[name], c[name]), name
+
+
+@pytest.mark.parametrize("N,M,T,chi", [(12, 10, 6.0, 64)])
+def test_large_bonds_match_oracle(P, N, M, T, chi):
+    """Bond dimensions above 32 (63 and 64, the full rank of the middle bond):
+    the global-scratch variant against the oracle."""
+    p = W.make_problem(task="ghz", N=N, M=M, T=T, chi=chi, K=2, R=1, sigma=0.5, seed=31,
+                       amp=2.0)
+    say(f"large bonds: ghz N={N} M={M} chi={chi}")
+    for k in range(p.K):
+        assert min(cut_gaps(p, k, 0)) >= 1e-8
+    res = _grape_case(P, p)
+    assert res["dcap"] > 32 and res["info"]["max_dim"] > 32
+    ref = og.fidelity_grad(p, details=True)
+    F = float(res["F"].cpu())
+    assert abs(F - ref["F"]) <= 1e-10 * abs(ref["F"])
+    for name in ("g_ux", "g_uy", "g_uzz"):
+        g = res[name].cpu().numpy()
+        gr = ref[name]
+        assert np.max(np.abs(g - gr)) <= 1e-10 * np.max(np.abs(gr)), name
+    O = res["overlaps"].cpu().numpy()
+    for (k, r), Or in ref["overlaps"].items():
+        assert abs(O[k, r] - Or) <= 1e-10 * max(abs(Or), 1e-6)

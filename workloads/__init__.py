@@ -26,12 +26,14 @@ Conventions shared by every consumer
 from __future__ import annotations
 
 import dataclasses
+import functools
 import math
 from typing import List, Optional
 
 import numpy as np
 
-__all__ = ["Problem", "CONFIGS", "make_problem", "haar_qubits"]
+__all__ = ["Problem", "CONFIGS", "make_problem", "haar_qubits", "heisenberg_ground_state",
+           "heisenberg_mps", "serving_mix"]
 
 
 @dataclasses.dataclass
@@ -113,7 +115,7 @@ def _masks(task: str, N: int):
         # u^zz on the pair bonds (2p, 2p+1), crosstalk on the bonds between
         # pairs (Sec. III, Eq. 11 with 0-based sites).
         return (b % 2 == 0).astype(np.uint8), (b % 2 == 1).astype(np.uint8)
-    if task in ("ghz", "state"):
+    if task in ("ghz", "heisenberg", "state"):
         return np.ones(N - 1, np.uint8), np.ones(N - 1, np.uint8)
     raise ValueError(f"unknown task {task!r}")
 
@@ -155,6 +157,69 @@ def ghz_mps(N: int) -> List[np.ndarray]:
     return [first] + [mid.copy() for _ in range(N - 2)] + [last]
 
 
+@functools.lru_cache(maxsize=4)
+def heisenberg_ground_state(N: int, tol: float = 1e-12):
+    """Ground state of the open chain H = sum_j (XX + YY + ZZ)_{j,j+1} on N
+    qubits (even N), by Lanczos (ARPACK) in the S^z = 0 sector, returned as a
+    dense real vector of length 2^N (bit j of the index is qubit j, 0 = |0>),
+    with its energy.  Used as a state-preparation target (Sec. IV)."""
+    import scipy.sparse.linalg as sla
+    if N % 2:
+        raise ValueError("even N required")
+    idx = np.arange(1 << N, dtype=np.int64)
+    pop = np.zeros(1 << N, np.int64)
+    for j in range(N):
+        pop += (idx >> j) & 1
+    basis = idx[pop == N // 2]
+    n = basis.size
+    diag = np.zeros(n)
+    hops = []
+    for b in range(N - 1):
+        differ = ((basis >> b) ^ (basis >> (b + 1))) & 1
+        diag += 1.0 - 2.0 * differ
+        src = np.nonzero(differ)[0]
+        dst = np.searchsorted(basis, basis[src] ^ (3 << b))
+        hops.append((src, dst))
+
+    def matvec(x):
+        x = np.asarray(x).reshape(-1)
+        y = diag * x
+        for src, dst in hops:
+            y[dst] += 2.0 * x[src]      # XX + YY swaps an antiparallel pair
+        return y
+
+    op = sla.LinearOperator((n, n), matvec=matvec, dtype=np.float64)
+    v0 = np.random.default_rng(N).standard_normal(n)
+    w, v = sla.eigsh(op, k=1, which="SA", v0=v0, tol=tol)
+    full = np.zeros(1 << N)
+    full[basis] = v[:, 0]
+    full /= np.linalg.norm(full)
+    return full, float(w[0])
+
+
+def heisenberg_mps(N: int = 20, chi: int = 64, eps: float = 1e-12) -> List[np.ndarray]:
+    """The Heisenberg ground state compressed to an MPS of bond dimension at
+    most chi by successive SVDs from the right (keeping the singular values
+    >= eps sigma_1), right-canonical with unit norm."""
+    psi, _ = heisenberg_ground_state(N)
+    # site order: site 0 is the most significant index of the reshaped
+    # vector, so bit j of the index must be qubit N-1-j: reverse the bits
+    t = psi.reshape((2,) * N).transpose(tuple(range(N - 1, -1, -1))).reshape(-1)
+    rest = t.astype(np.complex128)
+    sites: List[np.ndarray] = []
+    dr = 1
+    for j in range(N - 1, 0, -1):
+        mat = rest.reshape(-1, 2 * dr)
+        U, S, Vh = np.linalg.svd(mat, full_matrices=False)
+        k = int(max(1, min(chi, np.sum(S >= eps * S[0]))))
+        sites.append(Vh[:k].reshape(k, 2, dr).copy())
+        rest = U[:, :k] * S[:k]
+        dr = k
+    first = rest.reshape(1, 2, dr)
+    sites.append(first / np.linalg.norm(first))
+    return sites[::-1]
+
+
 def _targets(task: str, inputs: np.ndarray, N: int) -> List[List[np.ndarray]]:
     out = []
     for vecs in inputs:
@@ -171,6 +236,8 @@ def _targets(task: str, inputs: np.ndarray, N: int) -> List[List[np.ndarray]]:
             out.append(mps)
         elif task == "ghz":
             out.append(ghz_mps(N))
+        elif task == "heisenberg":
+            out.append([A.copy() for A in heisenberg_mps(N, 64)])
         else:
             raise ValueError(task)
     return out
@@ -229,7 +296,7 @@ def make_problem(name: Optional[str] = None, *, task: Optional[str] = None,
 
     J = rj.normal(0.0, sigma, (K, N - 1)) * crosstalk * xt_mask[None, :]
 
-    if task == "ghz":
+    if task in ("ghz", "heisenberg"):
         inputs = np.zeros((R, N, 2), np.complex128)
         inputs[..., 0] = 1.0
     else:
@@ -239,3 +306,25 @@ def make_problem(name: Optional[str] = None, *, task: Optional[str] = None,
                    renormalize=bool(renormalize), ux=ux, uy=uy, uzz=uzz,
                    zz_mask=zz_mask, xt_mask=xt_mask, J=J, inputs=inputs,
                    targets=targets, task=task, name=name or task)
+
+
+# Request mix of the serving workload: N in {10, 20, 30, 50}, chi in
+# {16, 32, 64, 128}, K in {8, 32, 128}, M uniform in 100..300, task in
+# {X gate, CNOT, GHZ, Heisenberg ground state (N = 20)}; R = 4 inputs for
+# gates, 1 for states; T = 10 for gates, N 2 pi / 8 for GHZ, N 2 pi / 2 for
+# the Heisenberg state (Sec. IV time scales); crosstalk sigma 0.02 for gates,
+# 0.05 for states.
+def serving_mix(n: int, seed: int = 4, ks=(8, 32, 128), ns=(10, 20, 30, 50),
+                chis=(16, 32, 64, 128), m_range=(100, 300)) -> List[dict]:
+    """n request specs (keyword arguments of make_problem) drawn from the mix."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        task = ("x", "cnot", "ghz", "heisenberg")[int(rng.integers(4))]
+        N = 20 if task == "heisenberg" else int(rng.choice(ns))
+        gate = task in ("x", "cnot")
+        T = 10.0 if gate else (N * 2 * math.pi / 8 if task == "ghz" else N * 2 * math.pi / 2)
+        out.append(dict(task=task, N=N, chi=int(rng.choice(chis)), K=int(rng.choice(ks)),
+                        M=int(rng.integers(m_range[0], m_range[1] + 1)), R=4 if gate else 1,
+                        T=T, sigma=0.02 if gate else 0.05, seed=1000 * seed + i))
+    return out
