@@ -251,7 +251,8 @@ int32_t tnrg_plan_threads(int32_t dcap);
  * its workspace did not fit is bypassed by at most max_bypass later ones.
  * The capacity bucket of each request is searched like the Python binding
  * does (4, 8, 16, 32, 64, 128 below min(chi, 2^(N/2)), then that value),
- * starting from the last bucket that worked for the same (N, M, chi, K, R);
+ * starting from the last bucket that worked for the same (N, M, chi, K, R)
+ * in any server of the process;
  * a request whose bonds outgrow its bucket is requeued at the head with the
  * next one.
  *
@@ -294,9 +295,13 @@ typedef struct {
   size_t arena_bytes, arena_free, arena_largest_free;
 } tnrg_server_info;
 
-/* n_streams in 1..16; max_bypass >= 0. */
+/* n_streams in 1..16; max_bypass >= 0; max_dcap: the largest capacity bucket
+ * a request may grow to (0: no limit); a request whose bonds need more
+ * completes with TNRG_EUNSUPPORTED (a service-level bound on the slow
+ * global-scratch capacities above 32). */
 int tnrg_server_create(void *arena, size_t arena_bytes, int32_t n_streams,
-                       int32_t max_bypass, tnrg_server **out);
+                       int32_t max_bypass, int32_t max_dcap,
+                       tnrg_server **out);
 /* Validates and queues a request; *ticket identifies its completion.  Does
  * not launch: tnrg_server_progress does. */
 int tnrg_server_submit(tnrg_server *s, const tnrg_request *req,

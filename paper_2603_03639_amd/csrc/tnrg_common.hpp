@@ -145,7 +145,7 @@ __host__ __device__ inline long long site_offset_slow(int N, int dcap, int j) {
 }
 
 // ----------------------------------------------------------------------------
-// Butterfly sums over aligned groups of G lanes (G = 1, 2, ..., 64) with DPP
+// Butterfly sums over aligned groups of G lanes (G = 1, 2, 4, 8, 16) with DPP
 // lane permutations.  Every step combines a lane with the partner of an
 // involution (row mirror, half-row mirror, xor 1, xor 2) as a + b on one side
 // and b + a on the other, so all G lanes end with bit-identical sums.
@@ -161,15 +161,19 @@ constexpr int kDppHalfMirror = 0x141; // lane i <-> 7-i within 8
 constexpr int kDppMirror = 0x140;     // lane i <-> 15-i within 16
 
 __device__ __forceinline__ double group_sum(double v, int G) {
-  // groups of 32 and 64 lanes (the larger capacities) first combine across
-  // rows with lane shuffles, then within rows as below
-  if (G >= 64) v += __shfl_xor(v, 32, 64);
-  if (G >= 32) v += __shfl_xor(v, 16, 64);
   if (G >= 16) v += dpp_d<kDppMirror>(v);
   if (G >= 8) v += dpp_d<kDppHalfMirror>(v);
   if (G >= 2) v += dpp_d<kDppXor1>(v);
   if (G >= 4) v += dpp_d<kDppXor2>(v);
   return v;
+}
+
+// Groups of 32 and 64 lanes (the larger capacities) first combine across rows
+// with lane shuffles (symmetric, so the lanes still agree bit for bit).
+__device__ __forceinline__ double group_sum_wide(double v, int G) {
+  if (G >= 64) v += __shfl_xor(v, 32, 64);
+  if (G >= 32) v += __shfl_xor(v, 16, 64);
+  return group_sum(v, G);
 }
 
 // Reciprocal square root and reciprocal from the hardware estimate refined by

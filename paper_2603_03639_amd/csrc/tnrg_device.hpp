@@ -16,8 +16,8 @@
 // larger capacities, whose working set exceeds the 160 KB of LDS).
 #include "tnrg_common.hpp"
 
-#if !defined(TNRG_NS) || !defined(TNRG_AS)
-#error "define TNRG_NS and TNRG_AS before including tnrg_device.hpp"
+#if !defined(TNRG_NS) || !defined(TNRG_AS) || !defined(TNRG_BIG)
+#error "define TNRG_NS, TNRG_AS and TNRG_BIG before including tnrg_device.hpp"
 #endif
 
 namespace TNRG_NS {
@@ -28,6 +28,18 @@ typedef TNRG_AS c2 sc2;
 typedef TNRG_AS double sdbl;
 typedef TNRG_AS int sint;
 typedef TNRG_AS long long sll;
+
+// The LDS variant serves capacities up to 32: bond problems of at most 64
+// columns (one value per lane in the wave-level pivot search and sort), lane
+// groups of at most 16 and, by the launch configuration, all column pairs of
+// a Jacobi round at once.  The global-scratch variant serves up to 256
+// columns (four values per lane), groups of up to 64 lanes and rounds with
+// more pairs than lane groups.
+constexpr bool kWide = TNRG_BIG;
+constexpr int kLaneQuads = TNRG_BIG ? 4 : 1;
+__device__ __forceinline__ double gsum(double v, int G) {
+  return kWide ? group_sum_wide(v, G) : group_sum(v, G);
+}
 
 typedef TNRG_AS Layout sLayout;
 __device__ __forceinline__ void layout_build(sLayout& L, int N, int dcap) {
@@ -162,8 +174,8 @@ __device__ __forceinline__ void lq_apply(Ctx& C, sc2* Z, int ldz, int j, int mz,
     c2 w = cmk(0.0, 0.0);
 #pragma unroll
     for (int i = 0; i < RQ; ++i) w = cfmac(v[i], z[i], w);
-    w.x = group_sum(w.x, G);
-    w.y = group_sum(w.y, G);
+    w.x = gsum(w.x, G);
+    w.y = gsum(w.y, G);
     const c2 cw = cscale(w, coef);
     double s = 0.0;
 #pragma unroll
@@ -172,7 +184,7 @@ __device__ __forceinline__ void lq_apply(Ctx& C, sc2* Z, int ldz, int j, int mz,
       zc[i] = z[i];
       if (r0 + i > j) s += cabs2(z[i]);
     }
-    s = group_sum(s, G);
+    s = gsum(s, G);
     if (q == 0) nrm[j + 1 + cc] = s;
   }
 }
@@ -191,7 +203,7 @@ __device__ __forceinline__ int lq_pivot(Ctx& C, sc2* Z, int nz, int mz, int ldz,
     for (int c = grp; c < mz; c += NT / G) {
       double s = 0.0;
       for (int i = 0; i < RQ; ++i) s += cabs2(Z[c * ldz + q * RQ + i]);
-      s = group_sum(s, G);
+      s = gsum(s, G);
       if (q == 0) {
         nrm[c] = s;
         pcol[c] = c;
@@ -201,7 +213,11 @@ __device__ __forceinline__ int lq_pivot(Ctx& C, sc2* Z, int nz, int mz, int ldz,
   __syncthreads();
   if (tid < 64) {
     double part = 0.0;
-    for (int c = tid; c < mz; c += 64) part += nrm[c];
+#pragma unroll
+    for (int q = 0; q < kLaneQuads; ++q) {
+      const int c = tid + 64 * q;
+      part += c < mz ? nrm[c] : 0.0;
+    }
     const double f2 = wave_sum(part);
     if (tid == 0) {
       const double lt = (double)mz * 2.220446049250313e-16;
@@ -216,7 +232,11 @@ __device__ __forceinline__ int lq_pivot(Ctx& C, sc2* Z, int nz, int mz, int ldz,
   for (int j = 0; j < steps; ++j) {
     if (tid < 64) {
       unsigned long long kk = 0ull;
-      for (int c = tid; c < mz; c += 64) kk = umax64(kk, c >= j ? argmax_key(nrm[c], c) : 0ull);
+#pragma unroll
+      for (int q = 0; q < kLaneQuads; ++q) {
+        const int c = tid + 64 * q;
+        kk = umax64(kk, (c >= j && c < mz) ? argmax_key(nrm[c], c) : 0ull);
+      }
       const unsigned long long key = wave_max_u64(kk);
       const int best = argmax_index(key);
       const double bv = nrm[best];
@@ -321,10 +341,10 @@ __device__ __forceinline__ int jacobi_sweep(Ctx& C, sc2* X, int ldx, int n, int 
       gr = fma(x[i].x, y[i].x, fma(x[i].y, y[i].y, gr));
       gi = fma(x[i].x, y[i].y, fma(-x[i].y, y[i].x, gi));
     }
-    a = group_sum(a, G);
-    b = group_sum(b, G);
-    gr = group_sum(gr, G);
-    gi = group_sum(gi, G);
+    a = gsum(a, G);
+    b = gsum(b, G);
+    gr = gsum(gr, G);
+    gi = gsum(gi, G);
     const double g2 = fma(gr, gr, gi * gi);
     const bool rot = valid && a > thr2 && b > thr2 && g2 > tol2 * a * b;
     rotated |= rot;
@@ -356,7 +376,7 @@ __device__ __forceinline__ int jacobi_sweep(Ctx& C, sc2* X, int ldx, int n, int 
   };
   // Round r of the circle schedule pairs column 0 with column 1 + r and,
   // for slot p = 1 .. P-1, column 1 + (p + r) mod m with 1 + (m - p + r) mod m.
-  if (P <= ngrp) {
+  if (!kWide || P <= ngrp) {
     // one slot per lane group: the positions advance by one each round
     const int pp = grp;
     int ia = (pp == 0) ? 0 : 1 + pp;
@@ -411,7 +431,7 @@ __device__ __forceinline__ int jacobi_lds(Ctx& C, sc2* X, int len, int ncol, int
       const sc2* xc = X + c * ldx + qc * Rc;
       double s = 0.0;
       for (int i = 0; i < Rc; ++i) s += cabs2(xc[i]);
-      s = group_sum(s, Gc);
+      s = gsum(s, Gc);
       if (qc == 0) C.sig[c] = s;
     }
   };
@@ -484,11 +504,11 @@ __device__ __forceinline__ int jacobi_lds(Ctx& C, sc2* X, int len, int ncol, int
 __device__ __forceinline__ void choose_k(Ctx& C, int n, int len, int capk) {
   if (C.tid < 64) {
     const int lane = C.tid;
-    double v[4];
-    int rk[4];
+    double v[kLaneQuads];
+    int rk[kLaneQuads];
     unsigned long long kk = 0ull;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < kLaneQuads; ++q) {
       v[q] = -1.0;
       rk[q] = 0;
       if (q * 64 < n) {
@@ -514,7 +534,7 @@ __device__ __forceinline__ void choose_k(Ctx& C, int n, int len, int capk) {
     const double smax = (key != 0ull) ? C.sig[argmax_index(key)] : 0.0;
     int k = 0;
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
+    for (int q = 0; q < kLaneQuads; ++q)
       if (q * 64 < n) k += __popcll(__ballot(lane + 64 * q < n && v[q] >= C.md.eps * smax));
     if (k > C.md.chi) k = C.md.chi;
     if (k < 1) k = 1;
@@ -527,7 +547,7 @@ __device__ __forceinline__ void choose_k(Ctx& C, int n, int len, int capk) {
     }
     double part = 0.0;
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
+    for (int q = 0; q < kLaneQuads; ++q)
       if (lane + 64 * q < n && rk[q] < k) part += v[q] * v[q];
     const double s2 = wave_sum(part);
     if (lane == 0) {

@@ -290,24 +290,28 @@ int check_batch(const tnrg_mps_batch* b, int N, const char* name) {
 // overrides this per capacity.
 std::atomic<int> g_plan_threads[kMaxSites + 1];
 
-// Default threads for capacity cap: enough that one Jacobi round processes
-// all of its up to cap column pairs at once with pow2(2 cap) / 8 lanes each
-// (8 rows per lane), at most 256.  Fewer threads loop over the pairs.
-int default_threads(int cap) {
+// Fewest threads for the LDS variant at capacity cap: every Jacobi round
+// processes up to cap column pairs at once with at least pow2(2 cap) / 8 lanes
+// each (8 rows per lane).  The global-scratch variant loops over the pairs of
+// a round and runs with any workgroup size.
+int min_threads_lds(int cap) {
   int p2 = 1;
   while (p2 < 2 * cap) p2 <<= 1;
   const int need = (p2 / 8 > 1 ? p2 / 8 : 1) * cap;
   int nt = 64;
-  while (nt < need && nt < 256) nt *= 2;
+  while (nt < need) nt *= 2;
   return nt;
 }
 
+bool use_lds(int cap);
+
 int threads_for_cap(int cap) {
+  const int lo = use_lds(cap) ? min_threads_lds(cap) : 64;
   if (cap >= 0 && cap <= kMaxSites) {
     const int t = g_plan_threads[cap].load(std::memory_order_relaxed);
-    if (t >= 64) return t;
+    if (t >= lo) return t;
   }
-  return default_threads(cap);
+  return use_lds(cap) ? lo : 256;
 }
 
 // Largest dynamic LDS a workgroup may use on gfx950.

@@ -17,6 +17,7 @@
 #include <deque>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <tuple>
 #include <vector>
@@ -124,19 +125,38 @@ struct Slot {
 
 using PlanKey = std::tuple<int, int, int, int, int>;  // N, M, chi, K, R
 
-std::vector<int> bucket_sequence(const tnrg_model& md, int start) {
+// The capacity-bucket plan: the last bucket that held every bond of a request
+// of this shape, shared by all servers of the process.
+std::mutex g_plan_mu;
+std::map<PlanKey, int> g_plan;
+
+int plan_get(const PlanKey& k) {
+  std::lock_guard<std::mutex> lk(g_plan_mu);
+  auto it = g_plan.find(k);
+  return it == g_plan.end() ? 0 : it->second;
+}
+void plan_put(const PlanKey& k, int cap) {
+  std::lock_guard<std::mutex> lk(g_plan_mu);
+  g_plan[k] = cap;
+}
+
+// Buckets to try: 4, 8, ... below min(chi, 2^(N/2)), then that value, all
+// at most max_dcap, starting from the plan's bucket `start` when there is one.
+std::vector<int> bucket_sequence(const tnrg_model& md, int start, int max_dcap) {
   const int half = md.n / 2;
   int cap_max = md.chi;
   if (half < 30 && (1 << half) < cap_max) cap_max = 1 << half;
   std::vector<int> seq;
   for (int b : {4, 8, 16, 32, 64, 128})
-    if (b < cap_max) seq.push_back(b);
-  seq.push_back(cap_max);
+    if (b < cap_max && b <= max_dcap) seq.push_back(b);
+  if (cap_max <= max_dcap) seq.push_back(cap_max);
+  if (seq.empty()) seq.push_back(max_dcap < cap_max ? max_dcap : cap_max);
   if (start > 0) {
     std::vector<int> tail;
     for (int b : seq)
       if (b >= start) tail.push_back(b);
-    if (!tail.empty()) seq.swap(tail);
+    if (tail.empty()) tail.push_back(seq.back());
+    seq.swap(tail);
   }
   return seq;
 }
@@ -149,8 +169,8 @@ struct tnrg_server {
   std::vector<Slot> slots;
   std::deque<std::unique_ptr<Job>> queue;
   std::deque<tnrg_completion> finished;
-  std::map<PlanKey, int> plan;
   int max_bypass = 0;
+  int max_dcap = 0;  // largest capacity bucket a request may use
   int64_t next_ticket = 1;
   int64_t submitted = 0, admitted = 0, completed = 0, regrown = 0, cancelled = 0;
 };
@@ -221,7 +241,13 @@ int reap(tnrg_server* s) {
       continue;
     }
     int status = TNRG_OK;
-    if (any & TNRG_FLAG_OVERFLOW)
+    const tnrg_model& jm = job->model;
+    int cap_max = jm.chi;
+    if (jm.n / 2 < 30 && (1 << (jm.n / 2)) < cap_max) cap_max = 1 << (jm.n / 2);
+    if ((any & TNRG_FLAG_OVERFLOW) && job->req.dcap == 0 && job->buckets[job->bucket] < cap_max)
+      status = err(TNRG_EUNSUPPORTED, "request needs a capacity above the server's max_dcap %d",
+                   s->max_dcap);
+    else if (any & TNRG_FLAG_OVERFLOW)
       status = TNRG_EOVERFLOW;
     else if (any & TNRG_FLAG_NOCONV)
       status = TNRG_ENOCONV;
@@ -229,7 +255,7 @@ int reap(tnrg_server* s) {
       status = TNRG_ENONFINITE;
     if (status == TNRG_OK && job->req.dcap == 0) {
       const tnrg_model& m = job->model;
-      s->plan[PlanKey(m.n, m.m, m.chi, job->req.K, job->req.R)] = job->buckets[job->bucket];
+      plan_put(PlanKey(m.n, m.m, m.chi, job->req.K, job->req.R), job->buckets[job->bucket]);
     }
     complete(s, std::move(job), status);
   }
@@ -292,15 +318,17 @@ void admit(tnrg_server* s) {
 extern "C" {
 
 int tnrg_server_create(void* arena, size_t arena_bytes, int32_t n_streams, int32_t max_bypass,
-                       tnrg_server** out) {
+                       int32_t max_dcap, tnrg_server** out) {
   if (!out) return err(TNRG_EINVAL, "NULL output pointer");
   *out = nullptr;
   if (!arena || arena_bytes < 256) return err(TNRG_EINVAL, "arena must be a device block of >= 256 bytes");
   if (n_streams < 1 || n_streams > 16) return err(TNRG_EINVAL, "n_streams = %d outside [1, 16]", n_streams);
   if (max_bypass < 0) return err(TNRG_EINVAL, "max_bypass < 0");
+  if (max_dcap < 0) return err(TNRG_EINVAL, "max_dcap < 0");
   std::unique_ptr<tnrg_server> s(new (std::nothrow) tnrg_server(static_cast<char*>(arena), arena_bytes));
   if (!s) return err(TNRG_ENOMEM, "host allocation failed");
   s->max_bypass = max_bypass;
+  s->max_dcap = max_dcap > 0 ? max_dcap : 1 << 30;
   s->slots.resize(n_streams);
   for (auto& sl : s->slots) {
     hipError_t e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking);
@@ -337,11 +365,13 @@ int tnrg_server_submit(tnrg_server* s, const tnrg_request* req, int64_t* ticket)
   job->tg = *req->targets;
   job->req.inputs = &job->in;
   job->req.targets = &job->tg;
+  if (req->dcap > s->max_dcap)
+    return err(TNRG_EUNSUPPORTED, "dcap %d above the server's max_dcap %d", req->dcap, s->max_dcap);
   if (req->dcap > 0) {
     job->buckets = {req->dcap};
   } else {
-    auto it = s->plan.find(PlanKey(md->n, md->m, md->chi, req->K, req->R));
-    job->buckets = bucket_sequence(job->model, it == s->plan.end() ? 0 : it->second);
+    job->buckets = bucket_sequence(job->model, plan_get(PlanKey(md->n, md->m, md->chi, req->K, req->R)),
+                                   s->max_dcap);
   }
   job->ticket = s->next_ticket++;
   job->t_submit = Clock::now();

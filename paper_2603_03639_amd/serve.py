@@ -61,11 +61,12 @@ class Request:
 
 class Server:
     def __init__(self, arena_bytes: int, n_streams: int = 4, max_bypass: int = 8,
-                 device="cuda"):
+                 max_dcap: int = 0, device="cuda"):
         self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device=device)
         h = tnrg._SP()
         tnrg._check(tnrg._lib.tnrg_server_create(tnrg._ptr(self.arena), self.arena.numel(),
-                                                 n_streams, max_bypass, ctypes.byref(h)))
+                                                 n_streams, max_bypass, max_dcap,
+                                                 ctypes.byref(h)))
         self._h = h
         self._live: Dict[int, tuple] = {}
 

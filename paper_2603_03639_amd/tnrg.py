@@ -110,7 +110,7 @@ _SIGS = {
                                       _i32, _dp, _dp, _dp, _vp, _vp, _sz, _vp]),
     "tnrg_status": (ctypes.c_int, [_vp, _i32, ctypes.POINTER(ctypes.c_int32),
                                    ctypes.POINTER(ctypes.c_int64), _vp]),
-    "tnrg_server_create": (ctypes.c_int, [_vp, _sz, _i32, _i32, ctypes.POINTER(_SP)]),
+    "tnrg_server_create": (ctypes.c_int, [_vp, _sz, _i32, _i32, _i32, ctypes.POINTER(_SP)]),
     "tnrg_server_submit": (ctypes.c_int, [_SP, ctypes.POINTER(_Request),
                                           ctypes.POINTER(ctypes.c_int64)]),
     "tnrg_server_progress": (ctypes.c_int, [_SP, ctypes.POINTER(_Completion), _i32,

@@ -5,7 +5,8 @@ different N, chi, M, K and R, admitted by workspace footprint.
     mix as alone (bit for bit when it ran in the same capacity bucket, else
     to 1e-10 relative);
   * an arena that holds two workspaces never runs more than two requests;
-  * a request whose bonds outgrow its bucket is regrown inside the server;
+  * a request whose bonds outgrow its bucket is regrown inside the server,
+    up to the server's largest admitted bucket;
   * a request too large for the arena fails alone with TNRG_ENOMEM;
   * queued requests can be cancelled.
 """
@@ -123,6 +124,12 @@ def test_bucket_regrowth_in_the_server(P):
     assert done[0]["status"] == 0 and done[0]["dcap"] == 16
     assert done[0]["launches"] >= 2 and info["regrown"] >= 1
     assert torch.equal(q.F, ref["F"]) and torch.equal(q.g_ux, ref["g_ux"])
+    # a server that admits buckets up to 8 refuses the same request
+    q2 = make_request(P, dict(spec, seed=9))
+    with P.serve.Server(arena_bytes=1 << 28, n_streams=1, max_dcap=8) as srv:
+        srv.submit(q2)
+        done = srv.drain()
+    assert done[0]["status"] == P.tnrg.EUNSUPPORTED and done[0]["dcap"] <= 8
 
 
 def test_too_large_and_cancel(P):
