@@ -76,7 +76,7 @@ def _reduction_consistent(p, res):
     assert np.max(np.abs(got - g)) <= 1e-12 * scale, np.max(np.abs(got - g)) / scale
 
 
-@pytest.mark.parametrize("name", ["cnot_n50", "cnot_n50_self", "xgate_n50"])
+@pytest.mark.parametrize("name", ["cnot_n50", "cnot_n50_self", "xgate_n50", "ghz_n30"])
 def test_full_size_sampled_trajectories(P, name):
     gold = GOLDEN[name]
     base = name[:-5] if name.endswith("_self") else name
