@@ -160,11 +160,13 @@ constexpr int kDppXor2 = 0x4E;        // quad_perm [2,3,0,1]
 constexpr int kDppHalfMirror = 0x141; // lane i <-> 7-i within 8
 constexpr int kDppMirror = 0x140;     // lane i <-> 15-i within 16
 
+// Inactive steps add +0 through a select instead of a branch, so the
+// reductions of several independent values interleave.
 __device__ __forceinline__ double group_sum(double v, int G) {
-  if (G >= 16) v += dpp_d<kDppMirror>(v);
-  if (G >= 8) v += dpp_d<kDppHalfMirror>(v);
-  if (G >= 2) v += dpp_d<kDppXor1>(v);
-  if (G >= 4) v += dpp_d<kDppXor2>(v);
+  v += (G >= 16) ? dpp_d<kDppMirror>(v) : 0.0;
+  v += (G >= 8) ? dpp_d<kDppHalfMirror>(v) : 0.0;
+  v += (G >= 2) ? dpp_d<kDppXor1>(v) : 0.0;
+  v += (G >= 4) ? dpp_d<kDppXor2>(v) : 0.0;
   return v;
 }
 

@@ -151,9 +151,38 @@ __device__ __forceinline__ void block_sum(Ctx& C, c2 (&v)[V]) {
 // (numerical rank).  Returns the rank (>= 1).  mz <= 256.
 // Scratch: nrm = C.sig (remaining squared norms by logical column), pcol =
 // C.perm (logical -> physical column of Z).
+// Per-lane register copies of a small table indexed by position c < 64 *
+// kLaneQuads: lane l holds the entries l, l + 64, ...  Every wave keeps its
+// own copy, updated identically, so the table needs no LDS or barrier.
+template <class T>
+__device__ __forceinline__ T quad_pick(const T (&r)[kLaneQuads], int q) {
+  T v = r[0];
+#pragma unroll
+  for (int i = 1; i < kLaneQuads; ++i) v = (q == i) ? r[i] : v;
+  return v;
+}
+// entry c (wave-uniform c)
+__device__ __forceinline__ int table_at(const int (&r)[kLaneQuads], int c) {
+  return __builtin_amdgcn_readlane(quad_pick(r, c >> 6), c & 63);
+}
+__device__ __forceinline__ double table_at(const double (&r)[kLaneQuads], int c) {
+  return readlane_d(quad_pick(r, c >> 6), c & 63);
+}
+// entry c (c per lane, 0 <= c < 64 kLaneQuads)
+__device__ __forceinline__ int table_gather(const int (&r)[kLaneQuads], int c) {
+  int out = 0;
+#pragma unroll
+  for (int i = 0; i < kLaneQuads; ++i) {
+    const int t = __shfl(r[i], c & 63, 64);
+    out = ((c >> 6) == i) ? t : out;
+  }
+  return out;
+}
+
 template <int RQ>
 __device__ __forceinline__ void lq_apply(Ctx& C, sc2* Z, int ldz, int j, int mz, int G, const sc2* zp, c2 v0,
-                         double coef, sdbl* nrm, const sint* pcol) {
+                         double coef, sdbl* nrm_next, const int (&pcol)[kLaneQuads], int best,
+                         int pj) {
   const int tid = C.tid, NT = C.nt;
   const int grp = tid / G, q = tid % G;
   const int ngrp = NT / G;
@@ -166,8 +195,17 @@ __device__ __forceinline__ void lq_apply(Ctx& C, sc2* Z, int ldz, int j, int mz,
     const c2 z = zp[row];
     v[i] = row < j ? cmk(0.0, 0.0) : (row == j ? v0 : z);
   }
-  for (int cc = grp; cc < mz - j - 1; cc += ngrp) {
-    sc2* zc = Z + pcol[j + 1 + cc] * ldz + r0;
+  const int ncols = mz - j - 1;
+  // the trip count is the same for every lane (the column map gather is a
+  // lane shuffle); groups past the last column work on nothing
+  for (int c0 = 0; c0 < ncols; c0 += ngrp) {
+    const int c = j + 1 + c0 + grp;
+    const bool live = c0 + grp < ncols;
+    // this step's pivot swap applies here: position best now holds the
+    // column that was at position j
+    const int phys = table_gather(pcol, live ? c : 0);
+    if (!live) continue;
+    sc2* zc = Z + (c == best ? pj : phys) * ldz + r0;
     c2 z[RQ];
 #pragma unroll
     for (int i = 0; i < RQ; ++i) z[i] = zc[i];
@@ -185,16 +223,23 @@ __device__ __forceinline__ void lq_apply(Ctx& C, sc2* Z, int ldz, int j, int mz,
       if (r0 + i > j) s += cabs2(z[i]);
     }
     s = gsum(s, G);
-    if (q == 0) nrm[j + 1 + cc] = s;
+    if (q == 0) nrm_next[c] = s;
   }
 }
 
+// The pivot search of a step runs in every wave on the same LDS values, so
+// the pivot, the Householder scalars and the stop decision are wave-uniform
+// registers everywhere and need no broadcast; the column map lives in
+// registers of every wave (updated identically) and the remaining column
+// norms are double buffered (read from one LDS buffer, the updated ones
+// written to the other), so a step needs a single barrier.  The R diagonal
+// of a step is written into Z at the start of the next step, when no wave
+// reads that element any more.
 __device__ __forceinline__ int lq_pivot(Ctx& C, sc2* Z, int nz, int mz, int ldz, sc2* X, int ldx, double* thr2_out) {
-  sdbl* sh_d = C.sd;
-  sint* sh_i = C.si;
   const int tid = C.tid, NT = C.nt;
+  const int lane = tid & 63;
   sdbl* nrm = C.sig;
-  sint* pcol = C.perm;
+  sdbl* nrm2 = (sdbl*)X;  // X is free until L is written into it
   const int padz = ldz;
   const int G = uniform(max(min(lanes_per(mz, NT), padz), padz / 8));
   const int RQ = uniform(padz / G);
@@ -204,83 +249,91 @@ __device__ __forceinline__ int lq_pivot(Ctx& C, sc2* Z, int nz, int mz, int ldz,
       double s = 0.0;
       for (int i = 0; i < RQ; ++i) s += cabs2(Z[c * ldz + q * RQ + i]);
       s = gsum(s, G);
-      if (q == 0) {
-        nrm[c] = s;
-        pcol[c] = c;
-      }
+      if (q == 0) nrm[c] = s;
     }
   }
+  int pcol[kLaneQuads];
+#pragma unroll
+  for (int q = 0; q < kLaneQuads; ++q) pcol[q] = lane + 64 * q;
   __syncthreads();
-  if (tid < 64) {
+  // threshold (len eps)^2 ||X||_F^2, computed by every wave
+  double thr2;
+  {
     double part = 0.0;
 #pragma unroll
     for (int q = 0; q < kLaneQuads; ++q) {
-      const int c = tid + 64 * q;
+      const int c = lane + 64 * q;
       part += c < mz ? nrm[c] : 0.0;
     }
     const double f2 = wave_sum(part);
-    if (tid == 0) {
-      const double lt = (double)mz * 2.220446049250313e-16;
-      sh_d[3] = lt * lt * f2;
-    }
+    const double lt = (double)mz * 2.220446049250313e-16;
+    thr2 = lt * lt * f2;
   }
-  __syncthreads();
-  const double thr2 = sh_d[3];
   *thr2_out = thr2;
   const int steps = nz < mz ? nz : mz;
   int rank = steps;
+  int pend_col = -1, pend_row = 0;
+  c2 pend_val = cmk(0.0, 0.0);
+  sdbl* cur = nrm;
+  sdbl* nxt = nrm2;
   for (int j = 0; j < steps; ++j) {
-    if (tid < 64) {
-      unsigned long long kk = 0ull;
+    if (tid == 0 && pend_col >= 0) Z[pend_col * ldz + pend_row] = pend_val;
+    double nv[kLaneQuads];
+    unsigned long long kk = 0ull;
 #pragma unroll
-      for (int q = 0; q < kLaneQuads; ++q) {
-        const int c = tid + 64 * q;
-        kk = umax64(kk, (c >= j && c < mz) ? argmax_key(nrm[c], c) : 0ull);
-      }
-      const unsigned long long key = wave_max_u64(kk);
-      const int best = argmax_index(key);
-      const double bv = nrm[best];
-      if (tid == 0) {
-        const int stop = !(key != 0ull && bv > thr2);
-        if (!stop) {
-          const int t = pcol[j];
-          pcol[j] = pcol[best];
-          pcol[best] = t;
-          nrm[best] = nrm[j];
-          nrm[j] = bv;
-          sc2* zj = Z + pcol[j] * ldz;
-          const c2 x0 = zj[j];
-          const double xn = bv * rsqrt_nr(bv);
-          const double a2 = cabs2(x0);
-          const double rax = a2 > 0.0 ? rsqrt_nr(a2) : 0.0;
-          const double ax0 = a2 * rax;
-          const c2 ph = a2 > 0.0 ? cscale(x0, rax) : cmk(1.0, 0.0);
-          // v = x + ph ||x|| e_j,  H x = -ph ||x|| e_j,  H = I - coef v v^dag
-          sh_d[0] = x0.x + ph.x * xn;
-          sh_d[1] = x0.y + ph.y * xn;
-          sh_d[2] = rcp_nr(xn * (xn + ax0));
-          zj[j] = cmk(-ph.x * xn, -ph.y * xn);
-        }
-        sh_i[0] = stop;
-      }
+    for (int q = 0; q < kLaneQuads; ++q) {
+      const int c = lane + 64 * q;
+      nv[q] = (c >= j && c < mz) ? cur[c] : 0.0;
+      kk = umax64(kk, (c >= j && c < mz) ? argmax_key(nv[q], c) : 0ull);
     }
-    __syncthreads();
-    if (sh_i[0]) {
+    const unsigned long long key = wave_max_u64(kk);
+    const int best = argmax_index(key);
+    const double bv = table_at(nv, best);
+    if (!(key != 0ull && bv > thr2)) {
       rank = j;
       break;
     }
     if (tid == 0) C.sstat[7] += 1;  // LQ steps
-    const c2 v0 = cmk(sh_d[0], sh_d[1]);
-    const double coef = sh_d[2];
-    const sc2* zp = Z + pcol[j] * ldz;
+    const int pj = table_at(pcol, j);
+    const int pb = table_at(pcol, best);
+    const sc2* zp = Z + pb * ldz;
+    const c2 x0 = zp[j];
+    const double xn = bv * rsqrt_nr(bv);
+    const double a2 = cabs2(x0);
+    const double rax = a2 > 0.0 ? rsqrt_nr(a2) : 0.0;
+    const double ax0 = a2 * rax;
+    const c2 ph = a2 > 0.0 ? cscale(x0, rax) : cmk(1.0, 0.0);
+    // v = x + ph ||x|| e_j,  H x = -ph ||x|| e_j,  H = I - coef v v^dag
+    const c2 v0 = cmk(x0.x + ph.x * xn, x0.y + ph.y * xn);
+    const double coef = rcp_nr(xn * (xn + ax0));
     switch (RQ) {
-      case 1: lq_apply<1>(C, Z, ldz, j, mz, G, zp, v0, coef, nrm, pcol); break;
-      case 2: lq_apply<2>(C, Z, ldz, j, mz, G, zp, v0, coef, nrm, pcol); break;
-      case 4: lq_apply<4>(C, Z, ldz, j, mz, G, zp, v0, coef, nrm, pcol); break;
-      default: lq_apply<8>(C, Z, ldz, j, mz, G, zp, v0, coef, nrm, pcol); break;
+      case 1: lq_apply<1>(C, Z, ldz, j, mz, G, zp, v0, coef, nxt, pcol, best, pj); break;
+      case 2: lq_apply<2>(C, Z, ldz, j, mz, G, zp, v0, coef, nxt, pcol, best, pj); break;
+      case 4: lq_apply<4>(C, Z, ldz, j, mz, G, zp, v0, coef, nxt, pcol, best, pj); break;
+      default: lq_apply<8>(C, Z, ldz, j, mz, G, zp, v0, coef, nxt, pcol, best, pj); break;
     }
+    // the swap in the column map
+#pragma unroll
+    for (int q = 0; q < kLaneQuads; ++q) {
+      const int c = lane + 64 * q;
+      pcol[q] = (c == j) ? pb : ((c == best) ? pj : pcol[q]);
+    }
+    pend_col = pb;
+    pend_row = j;
+    pend_val = cmk(-ph.x * xn, -ph.y * xn);
+    sdbl* t = cur;
+    cur = nxt;
+    nxt = t;
     __syncthreads();
   }
+  if (tid == 0 && pend_col >= 0) Z[pend_col * ldz + pend_row] = pend_val;
+  if (tid < 64) {
+#pragma unroll
+    for (int q = 0; q < kLaneQuads; ++q)
+      if (lane + 64 * q < mz) C.perm[lane + 64 * q] = pcol[q];
+  }
+  __syncthreads();
+  sint* pcolm = C.perm;
   if (rank < 1) rank = 1;  // a zero matrix still yields one (zero) column
   // L[pcol[c]][i] = conj(R[i][c]) = conj(Z[pcol[c]][i]) for i <= c, 0 below;
   // padding rows mz .. pad-1 of every column are zero.
@@ -290,7 +343,7 @@ __device__ __forceinline__ int lq_pivot(Ctx& C, sc2* Z, int nz, int mz, int ldz,
     c2 val = cmk(0.0, 0.0);
     int row = c;
     if (c < mz) {
-      row = pcol[c];
+      row = pcolm[c];
       if (i <= c) val = cconj(Z[row * ldz + i]);
     }
     X[i * ldx + row] = val;
