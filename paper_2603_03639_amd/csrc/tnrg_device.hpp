@@ -685,6 +685,7 @@ __device__ __forceinline__ int bond_split(Ctx& C, const sc2* Lt, const sc2* Rt, 
     const sc2* lp = Lt + row * dm;
     const sc2* rp = Rt + s2 * dr + c;
     c2 acc = cmk(0.0, 0.0);
+#pragma unroll 4
     for (int b = 0; b < dm; ++b) acc = cfma(lp[b], rp[b * 2 * dr], acc);
     acc = cmul(acc, s == s2 ? ph_same : ph_diff);
     if (ltr) {
@@ -929,6 +930,7 @@ __device__ __forceinline__ c2 left_envs(Ctx& C, const c2* bra, const int* bd, co
       const int rem = idx - s * bl * ar;
       const int z = rem / ar, y = rem - z * ar;
       c2 acc = cmk(0.0, 0.0);
+#pragma unroll 4
       for (int w = 0; w < al; ++w) acc = cfma(eb.E[z * al + w], A[(size_t)(w * 2 + s) * acap + y], acc);
       eb.TF[s * cc + z * ar + y] = acc;
     }
@@ -938,6 +940,7 @@ __device__ __forceinline__ c2 left_envs(Ctx& C, const c2* bra, const int* bd, co
       const int x = idx / ar, y = idx - x * ar;
       c2 acc = cmk(0.0, 0.0);
       for (int s = 0; s < 2; ++s)
+#pragma unroll 4
         for (int z = 0; z < bl; ++z)
           acc = cfmac(Bt[(size_t)(z * 2 + s) * bcap + x], eb.TF[s * cc + z * ar + y], acc);
       eb.E[idx] = acc;
