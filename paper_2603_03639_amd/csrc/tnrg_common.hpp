@@ -178,6 +178,56 @@ __device__ __forceinline__ double group_sum_wide(double v, int G) {
   return group_sum(v, G);
 }
 
+// The same butterfly for V independent values at once with a compile-time
+// group size 2^LG, so the steps of the V values interleave; the runtime
+// form branches once on the (wave-uniform) group size.  Wide adds the
+// cross-row steps for groups of 32 and 64 lanes.
+template <int LG, int V>
+__device__ __forceinline__ void group_sum_fixed(double (&v)[V]) {
+  if constexpr (LG >= 6) {
+#pragma unroll
+    for (int i = 0; i < V; ++i) v[i] += __shfl_xor(v[i], 32, 64);
+  }
+  if constexpr (LG >= 5) {
+#pragma unroll
+    for (int i = 0; i < V; ++i) v[i] += __shfl_xor(v[i], 16, 64);
+  }
+  if constexpr (LG >= 4) {
+#pragma unroll
+    for (int i = 0; i < V; ++i) v[i] += dpp_d<kDppMirror>(v[i]);
+  }
+  if constexpr (LG >= 3) {
+#pragma unroll
+    for (int i = 0; i < V; ++i) v[i] += dpp_d<kDppHalfMirror>(v[i]);
+  }
+  if constexpr (LG >= 1) {
+#pragma unroll
+    for (int i = 0; i < V; ++i) v[i] += dpp_d<kDppXor1>(v[i]);
+  }
+  if constexpr (LG >= 2) {
+#pragma unroll
+    for (int i = 0; i < V; ++i) v[i] += dpp_d<kDppXor2>(v[i]);
+  }
+}
+template <bool Wide, int V>
+__device__ __forceinline__ void group_sum_n(double (&v)[V], int G) {
+  switch (G) {
+    case 1: break;
+    case 2: group_sum_fixed<1>(v); break;
+    case 4: group_sum_fixed<2>(v); break;
+    case 8: group_sum_fixed<3>(v); break;
+    case 16: group_sum_fixed<4>(v); break;
+    default:
+      if constexpr (Wide) {
+        if (G == 32)
+          group_sum_fixed<5>(v);
+        else
+          group_sum_fixed<6>(v);
+      }
+      break;
+  }
+}
+
 // Reciprocal square root and reciprocal from the hardware estimate refined by
 // one Newton step (the estimate's relative error is squared away), so the
 // rotation parameters cost two short dependent chains instead of the IEEE

@@ -38,7 +38,9 @@ typedef TNRG_AS long long sll;
 constexpr bool kWide = TNRG_BIG;
 constexpr int kLaneQuads = TNRG_BIG ? 4 : 1;
 __device__ __forceinline__ double gsum(double v, int G) {
-  return kWide ? group_sum_wide(v, G) : group_sum(v, G);
+  double red[1] = {v};
+  group_sum_n<kWide>(red, G);
+  return red[0];
 }
 
 typedef TNRG_AS Layout sLayout;
@@ -212,8 +214,11 @@ __device__ __forceinline__ void lq_apply(Ctx& C, sc2* Z, int ldz, int j, int mz,
     c2 w = cmk(0.0, 0.0);
 #pragma unroll
     for (int i = 0; i < RQ; ++i) w = cfmac(v[i], z[i], w);
-    w.x = gsum(w.x, G);
-    w.y = gsum(w.y, G);
+    {
+      double red[2] = {w.x, w.y};
+      group_sum_n<kWide>(red, G);
+      w = cmk(red[0], red[1]);
+    }
     const c2 cw = cscale(w, coef);
     double s = 0.0;
 #pragma unroll
@@ -396,10 +401,14 @@ __device__ __forceinline__ int jacobi_sweep(Ctx& C, sc2* X, int ldx, int n, int 
       gr = fma(x[i].x, y[i].x, fma(x[i].y, y[i].y, gr));
       gi = fma(x[i].x, y[i].y, fma(-x[i].y, y[i].x, gi));
     }
-    a = gsum(a, G);
-    b = gsum(b, G);
-    gr = gsum(gr, G);
-    gi = gsum(gi, G);
+    {
+      double red[4] = {a, b, gr, gi};
+      group_sum_n<kWide>(red, G);
+      a = red[0];
+      b = red[1];
+      gr = red[2];
+      gi = red[3];
+    }
     const double g2 = fma(gr, gr, gi * gi);
     const bool rot = valid && a > thr2 && b > thr2 && g2 > tol2 * a * b;
     rotated |= rot ? 1 : 0;
@@ -487,8 +496,9 @@ __device__ __forceinline__ int jacobi_lds(Ctx& C, sc2* X, int len, int ncol, int
       const sc2* xc = X + c * ldx + qc * Rc;
       double s = 0.0;
       for (int i = 0; i < Rc; ++i) s += cabs2(xc[i]);
-      s = gsum(s, Gc);
-      if (qc == 0) C.sig[c] = s;
+      double red[1] = {s};
+      group_sum_n<kWide>(red, Gc);
+      if (qc == 0) C.sig[c] = red[0];
     }
   };
   for (int sw = 0; sw < max_sweeps && n >= 2; ++sw) {
@@ -519,17 +529,19 @@ __device__ __forceinline__ int jacobi_lds(Ctx& C, sc2* X, int len, int ncol, int
       // and pack the live ones to the front in order
       norms(n);
       __syncthreads();
-      if (tid == 0) {
-        int w = 0;
-        for (int c = 0; c < n; ++c) {
-          const int live = C.sig[c] > thr2;
-          C.perm[c] = live ? w : -1;
-          w += live;
-        }
-        C.si[1] = w;
+      // new positions by a prefix count of the live columns (every wave
+      // computes it; wave 0 writes the map)
+      int nn = 0;
+#pragma unroll
+      for (int q = 0; q < kLaneQuads; ++q) {
+        const int c = (tid & 63) + 64 * q;
+        const bool live = c < n && C.sig[c] > thr2;
+        const unsigned long long ball = __ballot(live);
+        const int before = __popcll(ball & ((1ull << (tid & 63)) - 1ull));
+        if (tid < 64 && c < n) C.perm[c] = live ? nn + before : -1;
+        nn += __popcll(ball);
       }
       __syncthreads();
-      const int nn = C.si[1];
       if (nn < n) {
         // move live column c to position perm[c] (<= c) in increasing order
         // of c, so no source is overwritten before it is read

@@ -67,3 +67,70 @@ def test_ghz_mps_matches_paper_fixture():
         ref[int(idx)] = amp
     assert np.abs(v - ref).max() < 1e-15
     assert abs(mps.norm(W.ghz_mps(30)) - 1.0) < 1e-14
+
+
+# ----------------------------------------------------------------------------
+# Heisenberg ground-state target of the serving mix (state preparation,
+# Sec. IV): Lanczos in the S^z = 0 sector, compressed to an MPS.
+def _dense_heisenberg(N):
+    X = np.array([[0, 1], [1, 0]], complex)
+    Y = np.array([[0, -1j], [1j, 0]])
+    Z = np.diag([1.0, -1.0]).astype(complex)
+    H = np.zeros((2 ** N, 2 ** N), complex)
+    for j in range(N - 1):
+        for P in (X, Y, Z):
+            ops = [np.eye(2)] * N
+            ops[j] = P
+            ops[j + 1] = P
+            # bit j of the index is qubit j: the kron order runs from qubit
+            # N-1 (most significant) down to qubit 0
+            M = np.array([[1.0]])
+            for q in range(N - 1, -1, -1):
+                M = np.kron(M, ops[q])
+            H += M
+    return H.real
+
+
+@pytest.mark.parametrize("N", [6, 8, 10])
+def test_heisenberg_ground_state_is_the_dense_one(N):
+    psi, E = W.heisenberg_ground_state(N)
+    w, v = np.linalg.eigh(_dense_heisenberg(N))
+    assert abs(E - w[0]) < 1e-10 * abs(w[0])
+    assert w[1] - w[0] > 1e-3                     # non-degenerate (singlet)
+    assert abs(abs(np.dot(v[:, 0], psi)) - 1.0) < 1e-10
+    H = _dense_heisenberg(N)
+    assert np.linalg.norm(H @ psi - E * psi) < 1e-9
+
+
+def test_heisenberg_ground_state_sector_and_mps():
+    N = 10
+    psi, E = W.heisenberg_ground_state(N)
+    idx = np.arange(2 ** N)
+    pop = np.array([bin(i).count("1") for i in idx])
+    assert np.all(psi[pop != N // 2] == 0.0)       # total S^z = 0
+    assert abs(np.linalg.norm(psi) - 1.0) < 1e-14
+    # with chi = 2^(N/2) the compression is exact
+    A = W.heisenberg_mps(N, chi=32)
+    v = mps.to_dense(A)
+    # to_dense puts site 0 first (most significant); psi has qubit j at bit j
+    t = psi.reshape((2,) * N).transpose(tuple(range(N - 1, -1, -1))).reshape(-1)
+    assert abs(abs(np.vdot(t, v)) - 1.0) < 1e-12
+    for j in range(1, N):
+        assert mps.is_right_isometric(A[j])
+    # a smaller chi truncates: still unit norm, overlap close to one
+    B = W.heisenberg_mps(N, chi=8)
+    assert max(a.shape[2] for a in B) == 8
+    assert abs(mps.norm(B) - 1.0) < 1e-12
+    assert abs(mps.overlap(B, A)) > 0.99
+
+
+def test_serving_mix_follows_the_recipe():
+    specs = W.serving_mix(200, seed=4)
+    assert {s["task"] for s in specs} == {"x", "cnot", "ghz", "heisenberg"}
+    for s in specs:
+        assert s["N"] in (10, 20, 30, 50) and s["chi"] in (16, 32, 64, 128)
+        assert s["K"] in (8, 32, 128) and 100 <= s["M"] <= 300
+        assert s["R"] == (4 if s["task"] in ("x", "cnot") else 1)
+        if s["task"] == "heisenberg":
+            assert s["N"] == 20
+    assert W.serving_mix(5, seed=4) == specs[:5]
