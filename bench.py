@@ -242,6 +242,9 @@ def main():
                     help="largest capacity bucket a served request may grow to (32: LDS path)")
     ap.add_argument("--serve-pool", type=int, default=24,
                     help="distinct requests drawn from the serving mix")
+    ap.add_argument("--ckpt-stride", type=int, default=None,
+                    help="checkpoint stride of the adjoint sweep (0: ceil(sqrt(M)); "
+                         "default: the smallest that fits 60%% of the free HBM)")
     ap.add_argument("--plain", type=int, default=8,
                     help="trajectories run one at a time for the plain GPU path (0 disables)")
     args = ap.parse_args()
@@ -280,7 +283,18 @@ def main():
     from paper_2603_03639_amd import tune
     tuned = tune.autotune(model, ux, uy, uzz, J, inputs, targets, plan["dcap"])
     log(f"autotune: {tuned}")
-    call = P.GrapeCall(model, p.K, p.R, inputs, targets, plan["dcap"], device=dev)
+    # checkpoint stride: keep as many forward states as 60% of the free HBM
+    # holds (stride 1 recomputes nothing); --ckpt-stride forces one
+    if args.ckpt_stride is None:
+        torch.cuda.empty_cache()
+        ck = tune.ckpt_stride(model, p.K, p.R, plan["dcap"])
+    else:
+        ck = {"stride": args.ckpt_stride,
+              "workspace_bytes": P.tnrg.grape_workspace_bytes(model, p.K, p.R, plan["dcap"],
+                                                              args.ckpt_stride)}
+    log(f"checkpoint stride {ck['stride']} (workspace {ck['workspace_bytes'] / 2**30:.1f} GiB)")
+    call = P.GrapeCall(model, p.K, p.R, inputs, targets, plan["dcap"], ckpt_stride=ck["stride"],
+                       device=dev)
     stream = torch.cuda.current_stream()
 
     for i in range(args.warmup):
@@ -306,6 +320,8 @@ def main():
     ms = 1000.0 * wall / args.steps
     value = p.K / (ms / 1000.0)
     F = float(call.F.cpu())
+    del call  # its workspace (up to a third of the HBM) is not needed any more
+    torch.cuda.empty_cache()
 
     flops = info["jacobi_flops"] + info["contraction_flops"]
     kern_ms = sum(lat) / len(lat)
@@ -332,7 +348,8 @@ def main():
     if args.profile:
         import dataclasses
         mprof = dataclasses.replace(model, profile=True)
-        pc = P.GrapeCall(mprof, p.K, p.R, inputs, targets, plan["dcap"], device=dev)
+        pc = P.GrapeCall(mprof, p.K, p.R, inputs, targets, plan["dcap"],
+                         ckpt_stride=ck["stride"], device=dev)
         pc.run(ux, uy, uzz, J)
         pinfo = pc.check()
         ticks = pinfo["phase_ticks"]
@@ -360,7 +377,8 @@ def main():
                   for r in range(n)]
         one_tg = [P.MPSBatch(p.N, 1, sub_tg.dcap, dev, sub_tg.data[r:r + 1], sub_tg.dims[r:r + 1])
                   for r in range(n)]
-        calls = [P.GrapeCall(model, 1, 1, one_in[r], one_tg[r], plan["dcap"], device=dev)
+        calls = [P.GrapeCall(model, 1, 1, one_in[r], one_tg[r], plan["dcap"],
+                             ckpt_stride=ck["stride"], device=dev)
                  for r in range(n)]
         Jk = J[0:1].contiguous()
         torch.cuda.synchronize()
@@ -397,6 +415,7 @@ def main():
                                f"K={p.K} noise samples x R={p.R} inputs, T={p.T}",
                    "N": p.N, "chi": p.chi, "M": p.M, "K": p.K, "R": p.R,
                    "dcap": plan["dcap"], "max_bond_dim": info["max_dim"],
+                   "ckpt_stride": ck["stride"], "workspace_gib": ck["workspace_bytes"] / 2**30,
                    "threads_per_trajectory": tune.threads(plan["dcap"])},
         "autotune": tuned,
         "trajectories_per_s": value * p.R,

@@ -1,4 +1,5 @@
-"""Launch-plan autotuner: workgroup size per capacity bucket.
+"""Launch-plan autotuner: workgroup size per capacity bucket, and the
+checkpoint stride of the adjoint sweep under an HBM budget.
 
 The persistent kernel runs one workgroup per trajectory.  With few
 trajectories per SIMD the bond update is latency-bound, and 2 or 4 waves per
@@ -61,3 +62,27 @@ def autotune(model: "tnrg.Model", ux, uy, uzz, J, inputs: "tnrg.MPSBatch",
     set_threads(dcap, win)
     _tuned[key] = win
     return {"threads": win, "cached": False, "seconds": times, "slices": Ms}
+
+
+def ckpt_stride(model: "tnrg.Model", K: int, R: int, dcap: int, budget_bytes=None,
+                frac: float = 0.6) -> dict:
+    """Smallest checkpoint stride whose workspace fits the HBM budget.
+
+    With stride s the forward pass keeps every s-th state and the adjoint
+    sweep recomputes the states in between, (M - M/s) extra slices per
+    trajectory; s = 1 keeps every forward state and recomputes nothing.  The
+    default budget is ``frac`` of the device memory free now.  Returns the
+    stride (0, the library's ceil(sqrt(M)), when even that does not fit) and
+    the workspace bytes it needs.
+    """
+    if budget_bytes is None:
+        free, _total = torch.cuda.mem_get_info()
+        budget_bytes = int(frac * free)
+    import math
+    top = max(1, math.ceil(math.sqrt(model.M)))
+    for s in range(1, top + 1):
+        need = tnrg.grape_workspace_bytes(model, K, R, dcap, s)
+        if need <= budget_bytes:
+            return {"stride": s, "workspace_bytes": need, "budget_bytes": budget_bytes}
+    return {"stride": 0, "workspace_bytes": tnrg.grape_workspace_bytes(model, K, R, dcap, 0),
+            "budget_bytes": budget_bytes}
