@@ -361,8 +361,9 @@ __device__ __forceinline__ int lq_pivot(Ctx& C, sc2* Z, int nz, int mz, int ldz,
 // One-sided (Hestenes) Jacobi SVD of the len x ncol matrix X held column-major
 // in LDS (column c at X + c*ldx, rows padded with zeros to pad = pow2(len)).
 // Columns are rotated pairwise until every pair is orthogonal to len * 2^-52
-// relative to the column norms (a sweep whose rotations were all below 1e-9
-// in |sin| ends the iteration: the next one could only find O(1e-18)); the
+// relative to the column norms (a sweep whose rotations all had
+// |sin|^2 < 2^-52 ends the iteration: the cosines it leaves are at most about
+// n 2^-52 <= len 2^-52, so the next sweep would rotate nothing); the
 // columns then hold sigma_i u_i.  Pairs
 // are visited in the round-robin (circle) order, all disjoint pairs of a
 // round in parallel; each pair's rows are split over G lanes whose partial
@@ -381,7 +382,7 @@ __device__ __forceinline__ int jacobi_sweep(Ctx& C, sc2* X, int ldx, int n, int 
   const int grp = tid / G, q = tid % G;
   const int ngrp = C.nt / G;
   const int r0 = q * RPL;
-  int rotated = 0;  // bit 0: a rotation; bit 1: a rotation with |sin| >= 1e-9
+  int rotated = 0;  // bit 0: a rotation; bit 1: a rotation with |sin|^2 >= 2^-52
   // one pair (ia, ib) of one round; idle slots work on two scratch columns
   // nobody reads, so the round is straight-line code without lane masking
   auto pair = [&](int ia, int ib, bool valid) {
@@ -425,7 +426,7 @@ __device__ __forceinline__ int jacobi_sweep(Ctx& C, sc2* X, int ldx, int n, int 
     const double cs = rot ? fma(s2, rh, ad) * w : 1.0;
     const double sw2 = rot ? (d >= 0.0 ? 2.0 : -2.0) * w : 0.0;
     const double pr = sw2 * gr, pi = sw2 * gi;  // s e
-    rotated |= (rot && sw2 * sw2 * g2 >= 1e-18) ? 2 : 0;
+    rotated |= (rot && sw2 * sw2 * g2 >= 2.220446049250313e-16) ? 2 : 0;
 #pragma unroll
     for (int i = 0; i < RPL; ++i) {
       c2 xn, yn;
@@ -520,9 +521,9 @@ __device__ __forceinline__ int jacobi_lds(Ctx& C, sc2* X, int len, int ncol, int
     }
     ph_add(C, kPhJacRounds, tj);
     const int any = __syncthreads_or(rotated & 1);
-    // Quadratic convergence: after a sweep whose rotations all had
-    // |sin| < 1e-9 every pair is orthogonal to O(1e-18) relative, far below
-    // the tolerance, so the confirming sweep without rotations is skipped.
+    // Quadratic convergence: a sweep whose rotations all had |sin|^2 < 2^-52
+    // leaves cosines of at most about n 2^-52, within the tolerance len 2^-52,
+    // so the confirming sweep without rotations is skipped.
     const int anybig = __syncthreads_or(rotated & 2);
     if (sw == 0 && any) {
       // after the first sweep, drop the columns that sank to rounding level
