@@ -77,15 +77,17 @@ def sources_sha256():
     return h.hexdigest()
 
 
-def stored_traffic(workload):
+def stored_traffic(workload, ckpt_stride):
     """HBM bytes per launch from the committed FETCH_SIZE/WRITE_SIZE runs, or
-    None when the kernel sources changed since those counters were taken."""
+    None when the kernel sources or the checkpoint stride changed since those
+    counters were taken."""
     path = os.path.join(ROOT, "profiles", f"k_grape_{workload}_hbm.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         rec = json.load(fh)
-    return rec["bytes_per_launch"] if rec.get("sources_sha256") == sources_sha256() else None
+    ok = rec.get("sources_sha256") == sources_sha256() and rec.get("ckpt_stride") == ckpt_stride
+    return rec["bytes_per_launch"] if ok else None
 
 
 def _request_pool(P, W, dev, n, seed=4):
@@ -328,7 +330,7 @@ def main():
     achieved = flops / (kern_ms / 1000.0) / 1e12
     roofline = {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
-                "traffic": stored_traffic(args.workload),
+                "traffic": stored_traffic(args.workload, ck["stride"]),
                 "kernel": "k_grape", "flops_per_launch": flops,
                 "jacobi_flops_per_launch": info["jacobi_flops"],
                 "contraction_flops_per_launch": info["contraction_flops"],
