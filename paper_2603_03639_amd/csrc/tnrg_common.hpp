@@ -228,6 +228,27 @@ __device__ __forceinline__ void group_sum_n(double (&v)[V], int G) {
   }
 }
 
+// idx = start, start + step, ... split as idx = q W + r without a division
+// per element (an integer division by a runtime divisor costs tens of
+// instructions on this ISA): the quotient and remainder advance by those of
+// the step.
+struct DivWalk {
+  int idx, q, r;
+  int step, dq, dr, W;
+  __device__ __forceinline__ DivWalk(int start, int step_, int W_)
+      : idx(start), q(start / W_), r(start - (start / W_) * W_), step(step_), dq(step_ / W_),
+        dr(step_ - (step_ / W_) * W_), W(W_) {}
+  __device__ __forceinline__ void next() {
+    idx += step;
+    q += dq;
+    r += dr;
+    if (r >= W) {
+      r -= W;
+      ++q;
+    }
+  }
+};
+
 // Reciprocal square root and reciprocal from the hardware estimate refined by
 // one Newton step (the estimate's relative error is squared away), so the
 // rotation parameters cost two short dependent chains instead of the IEEE

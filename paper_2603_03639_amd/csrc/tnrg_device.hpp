@@ -343,8 +343,8 @@ __device__ __forceinline__ int lq_pivot(Ctx& C, sc2* Z, int nz, int mz, int ldz,
   // L[pcol[c]][i] = conj(R[i][c]) = conj(Z[pcol[c]][i]) for i <= c, 0 below;
   // padding rows mz .. pad-1 of every column are zero.
   const int padx = pow2_at_least(mz);
-  for (int idx = tid; idx < rank * padx; idx += NT) {
-    const int i = idx / padx, c = idx - i * padx;
+  for (DivWalk w(tid, NT, padx); w.idx < rank * padx; w.next()) {
+    const int i = w.q, c = w.r;
     c2 val = cmk(0.0, 0.0);
     int row = c;
     if (c < mz) {
@@ -641,24 +641,22 @@ __device__ __forceinline__ void choose_k(Ctx& C, int n, int len, int capk) {
 __device__ __forceinline__ void load_site(Ctx& C, sc2* dst, const c2* site, int dl, int dr, int capr,
                           const M22& G) {
   const int n = dl * 2 * dr;
-  for (int idx = C.tid; idx < n; idx += C.nt) {
-    const int a = idx / (2 * dr);
-    const int rem = idx - a * 2 * dr;
-    const int s = rem / dr;
-    const int c = rem - s * dr;
+  for (DivWalk w(C.tid, C.nt, 2 * dr); w.idx < n; w.next()) {
+    const int a = w.q;
+    const int s = w.r >= dr ? 1 : 0;
+    const int c = w.r - s * dr;
     const c2 x0 = site[(size_t)(a * 2 + 0) * capr + c];
     const c2 x1 = site[(size_t)(a * 2 + 1) * capr + c];
-    dst[idx] = m22_row(G, s, x0, x1);
+    dst[w.idx] = m22_row(G, s, x0, x1);
   }
 }
 __device__ __forceinline__ void store_site(Ctx& C, c2* site, const sc2* src, int dl, int dr, int capr,
                            const M22& G) {
   const int n = dl * 2 * dr;
-  for (int idx = C.tid; idx < n; idx += C.nt) {
-    const int a = idx / (2 * dr);
-    const int rem = idx - a * 2 * dr;
-    const int s = rem / dr;
-    const int c = rem - s * dr;
+  for (DivWalk w(C.tid, C.nt, 2 * dr); w.idx < n; w.next()) {
+    const int a = w.q;
+    const int s = w.r >= dr ? 1 : 0;
+    const int c = w.r - s * dr;
     const c2 x0 = src[(a * 2 + 0) * dr + c];
     const c2 x1 = src[(a * 2 + 1) * dr + c];
     site[(size_t)(a * 2 + s) * capr + c] = m22_row(G, s, x0, x1);
@@ -689,11 +687,11 @@ __device__ __forceinline__ int bond_split(Ctx& C, const sc2* Lt, const sc2* Rt, 
   const c2 ph_diff = cmk(cp, sp);   // exp(+i phi)   (z_s z_s' = -1)
   // theta[(a,s),(s',c)] = P[s][s'] sum_b Lt[a,s,b] Rt[b,s',c]
   const int nth = 4 * dl * dr;
-  for (int idx = C.tid; idx < nth; idx += C.nt) {
-    const int row = idx / (2 * dr);
-    const int col = idx - row * 2 * dr;
+  for (DivWalk w(C.tid, C.nt, 2 * dr); w.idx < nth; w.next()) {
+    const int row = w.q;
+    const int col = w.r;
     const int s = row & 1;
-    const int s2 = col / dr;
+    const int s2 = col >= dr ? 1 : 0;
     const int c = col - s2 * dr;
     const sc2* lp = Lt + row * dm;
     const sc2* rp = Rt + s2 * dr + c;
@@ -714,9 +712,9 @@ __device__ __forceinline__ int bond_split(Ctx& C, const sc2* Lt, const sc2* Rt, 
   // L (len x rank) in X
   sc2* Z = C.LC;
   const int ldz = pow2_at_least(nc);
-  for (int idx = C.tid; idx < len * ldz; idx += C.nt) {
-    const int r = idx / ldz, c = idx - r * ldz;
-    Z[idx] = c < nc ? cconj(X[c * ldx + r]) : cmk(0.0, 0.0);
+  for (DivWalk w(C.tid, C.nt, ldz); w.idx < len * ldz; w.next()) {
+    const int r = w.q, c = w.r;
+    Z[w.idx] = c < nc ? cconj(X[c * ldx + r]) : cmk(0.0, 0.0);
   }
   __syncthreads();
   ph_add(C, kPhTheta, t0);
@@ -738,9 +736,10 @@ __device__ __forceinline__ int bond_split(Ctx& C, const sc2* Lt, const sc2* Rt, 
   if (C.tid == 0) C.sstat[5] += 8LL * k * nc * len;  // Q^dag theta
   // Q_i = X_{perm i} / sig_{perm i}  -> LO  (len x k, column i at LO + i*len)
   sc2* Q = C.LO;
-  for (int idx = C.tid; idx < k * len; idx += C.nt) {
-    const int i = idx / len;
-    const int r = idx - i * len;
+  for (DivWalk w(C.tid, C.nt, len); w.idx < k * len; w.next()) {
+    const int i = w.q;
+    const int r = w.r;
+    const int idx = w.idx;
     const int c = C.perm[i];
     Q[idx] = cscale(X[c * ldx + r], 1.0 / C.sig[c]);
   }
@@ -749,9 +748,9 @@ __device__ __forceinline__ int bond_split(Ctx& C, const sc2* Lt, const sc2* Rt, 
   for (int idx = C.tid; idx < nc * ldx; idx += C.nt) X[idx] = X0[idx];
   __syncthreads();
   // Dm[i][c] = sum_r conj(Q_i[r]) theta_c[r]  -> new centre in LC
-  for (int idx = C.tid; idx < k * nc; idx += C.nt) {
-    const int i = idx / nc;
-    const int c = idx - i * nc;
+  for (DivWalk w(C.tid, C.nt, nc); w.idx < k * nc; w.next()) {
+    const int i = w.q;
+    const int c = w.r;
     const sc2* qi = Q + i * len;
     const sc2* xc = X + c * ldx;
     c2 acc = cmk(0.0, 0.0);
@@ -766,11 +765,10 @@ __device__ __forceinline__ int bond_split(Ctx& C, const sc2* Lt, const sc2* Rt, 
   if (ltr) {
     // site b: (dl, 2, k), A[a,s,i] = sum_t G[s][t] Q_i[a*2+t]
     const int n = dl * 2 * k;
-    for (int idx = C.tid; idx < n; idx += C.nt) {
-      const int a = idx / (2 * k);
-      const int rem = idx - a * 2 * k;
-      const int s = rem / k;
-      const int i = rem - s * k;
+    for (DivWalk w(C.tid, C.nt, 2 * k); w.idx < n; w.next()) {
+      const int a = w.q;
+      const int s = w.r >= k ? 1 : 0;
+      const int i = w.r - s * k;
       const c2 q0 = Q[i * len + a * 2 + 0];
       const c2 q1 = Q[i * len + a * 2 + 1];
       iso[(size_t)(a * 2 + s) * iso_capr + i] = m22_row(Gfin, s, q0, q1);
@@ -778,11 +776,10 @@ __device__ __forceinline__ int bond_split(Ctx& C, const sc2* Lt, const sc2* Rt, 
   } else {
     // site b+1: (k, 2, dr), A[i,s,c] = sum_t G[s][t] conj(Q_i[t*dr + c])
     const int n = k * 2 * dr;
-    for (int idx = C.tid; idx < n; idx += C.nt) {
-      const int i = idx / (2 * dr);
-      const int rem = idx - i * 2 * dr;
-      const int s = rem / dr;
-      const int c = rem - s * dr;
+    for (DivWalk w(C.tid, C.nt, 2 * dr); w.idx < n; w.next()) {
+      const int i = w.q;
+      const int s = w.r >= dr ? 1 : 0;
+      const int c = w.r - s * dr;
       const c2 q0 = cconj(Q[i * len + c]);
       const c2 q1 = cconj(Q[i * len + dr + c]);
       iso[(size_t)(i * 2 + s) * iso_capr + c] = m22_row(Gfin, s, q0, q1);
@@ -892,8 +889,8 @@ __device__ __forceinline__ void copy_mps(Ctx& C, const c2* src, const int* sdims
     const int dl = C.sdims[j], dr = C.sdims[j + 1];
     const int scr = bond_cap(N, sdcap, j + 1);
     const int n = dl * 2 * dr;
-    for (int idx = C.tid; idx < n; idx += C.nt) {
-      const int row = idx / dr, c = idx - row * dr;
+    for (DivWalk w(C.tid, C.nt, dr); w.idx < n; w.next()) {
+      const int row = w.q, c = w.r;
       dst[Ld.off[j] + (size_t)row * Ld.cap[j + 1] + c] = src[soff + (size_t)row * scr + c];
     }
     soff += (long long)bond_cap(N, sdcap, j) * 2 * scr;
@@ -938,10 +935,9 @@ __device__ __forceinline__ c2 left_envs(Ctx& C, const c2* bra, const int* bd, co
     const int bcap = Lb.cap[j + 1];
     if (C.tid == 0) C.sstat[5] += 16LL * (bl * ar * al + br * ar * bl);
     // T[s][z][y] = sum_w E[z][w] A[w,s,y]   (bl x ar)
-    for (int idx = C.tid; idx < 2 * bl * ar; idx += C.nt) {
-      const int s = idx / (bl * ar);
-      const int rem = idx - s * bl * ar;
-      const int z = rem / ar, y = rem - z * ar;
+    for (DivWalk w(C.tid, C.nt, ar); w.idx < 2 * bl * ar; w.next()) {
+      const int s = w.q >= bl ? 1 : 0;
+      const int z = w.q - s * bl, y = w.r;
       c2 acc = cmk(0.0, 0.0);
 #pragma unroll 4
       for (int w = 0; w < al; ++w) acc = cfma(eb.E[z * al + w], A[(size_t)(w * 2 + s) * acap + y], acc);
@@ -949,8 +945,9 @@ __device__ __forceinline__ c2 left_envs(Ctx& C, const c2* bra, const int* bd, co
     }
     __syncthreads();
     // E'[x][y] = sum_s sum_z conj(B[z,s,x]) T[s][z][y]   (br x ar)
-    for (int idx = C.tid; idx < br * ar; idx += C.nt) {
-      const int x = idx / ar, y = idx - x * ar;
+    for (DivWalk w(C.tid, C.nt, ar); w.idx < br * ar; w.next()) {
+      const int x = w.q, y = w.r;
+      const int idx = w.idx;
       c2 acc = cmk(0.0, 0.0);
       for (int s = 0; s < 2; ++s)
 #pragma unroll 4
