@@ -9,7 +9,8 @@ from .tnrg import (Model, MPSBatch, GrapeCall, TnrgError, grape_fidelity_grad,  
                    fidelity, mps_evolve, mps_overlap)
 from .autograd import EnsembleFidelity, ensemble_fidelity  # noqa: F401
 from . import serve  # noqa: F401
+from . import optimize  # noqa: F401
 
 __all__ = ["tnrg", "Model", "MPSBatch", "GrapeCall", "TnrgError", "grape_fidelity_grad",
            "fidelity", "mps_evolve", "mps_overlap", "EnsembleFidelity", "ensemble_fidelity",
-           "serve"]
+           "serve", "optimize"]
