@@ -8,7 +8,13 @@ length dt is split second-order as U = R Z R (Strang), where
     Z = exp(-i dt sum_b c_b Z_b Z_{b+1})   (all ZZ terms commute, so exact),
 
 the rightmost factor acting first.  The paper's Eq. 4 is the first-order
-product of the same three kinds of factor.
+product of the same three kinds of factor, U = X Y Z with
+
+    X = exp(-i dt u^x X / 2),   Y = exp(-i dt u^y Y / 2)   on every site;
+
+``problem.order`` (2, the default, or 1) selects the split.  Either way a
+slice is U = post . Z . pre with per-site 2x2 factors: pre = post = R
+(second order) or pre = I, post = X Y (first order).
 """
 from __future__ import annotations
 
@@ -74,3 +80,44 @@ def slice_rotations(problem, l: int) -> np.ndarray:
     """R[j] for slice l (0-based), shape (N, 2, 2)."""
     return np.array([half_rotation(problem.ux[l, j], problem.uy[l, j],
                                    problem.dt) for j in range(problem.N)])
+
+
+def first_order_rotation(ux: float, uy: float, dt: float) -> np.ndarray:
+    """G = exp(-i dt ux X/2) exp(-i dt uy Y/2) (the X and Y layers of Eq. 4)."""
+    cx, sx = np.cos(dt * ux / 2.0), np.sin(dt * ux / 2.0)
+    cy, sy = np.cos(dt * uy / 2.0), np.sin(dt * uy / 2.0)
+    return (cx * I2 - 1j * sx * X) @ (cy * I2 - 1j * sy * Y)
+
+
+def first_order_rotation_derivs(ux: float, uy: float, dt: float):
+    """(dG/dux, dG/duy): (-i dt/2 X) G and exp(-i dt ux X/2) (-i dt/2 Y) exp(-i dt uy Y/2)."""
+    cx, sx = np.cos(dt * ux / 2.0), np.sin(dt * ux / 2.0)
+    cy, sy = np.cos(dt * uy / 2.0), np.sin(dt * uy / 2.0)
+    Xr = cx * I2 - 1j * sx * X
+    Yr = cy * I2 - 1j * sy * Y
+    return (-0.5j * dt) * X @ Xr @ Yr, Xr @ ((-0.5j * dt) * Y) @ Yr
+
+
+def order(problem) -> int:
+    return int(getattr(problem, "order", 2))
+
+
+def site_factors(problem, l: int, j: int):
+    """(pre, post, dpre, dpost) of site j in slice l (0-based); dpre and dpost
+    are (d/dux, d/duy) pairs, dpre None where pre does not depend on u."""
+    ux, uy, dt = problem.ux[l, j], problem.uy[l, j], problem.dt
+    if order(problem) == 1:
+        return I2, first_order_rotation(ux, uy, dt), None, first_order_rotation_derivs(ux, uy, dt)
+    R = half_rotation(ux, uy, dt)
+    d = half_rotation_derivs(ux, uy, dt)
+    return R, R, d, d
+
+
+def slice_pre(problem, l: int) -> np.ndarray:
+    """pre[j] of slice l, shape (N, 2, 2)."""
+    return np.array([site_factors(problem, l, j)[0] for j in range(problem.N)])
+
+
+def slice_post(problem, l: int) -> np.ndarray:
+    """post[j] of slice l, shape (N, 2, 2)."""
+    return np.array([site_factors(problem, l, j)[1] for j in range(problem.N)])

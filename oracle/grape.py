@@ -14,6 +14,11 @@ the control enters.  For the second-order slice U_l = R_l Z_l R_l:
   * ZZ control of slice l on bond b:
         G = -i dt (R_{l,b} Z R_{l,b}^dagger) (x) (R_{l,b+1} Z R_{l,b+1}^dagger)
 
+For the paper's first-order split U_l = X_l Y_l Z_l only the outer factor
+P = X_l Y_l depends on the drive: G = dP P^dagger (that is -i dt/2 X and
+X_l (-i dt/2 Y) X_l^dagger, the insertions of App. A with their -i dt
+factor) and the ZZ insertion uses P in place of R.
+
 (the paper's Eq. A2 shows the first-order form without the -i dt factor; the
 factor and the positions follow from differentiating the slice).  All matrix
 elements at one boundary come from one pass of left/right transfer
@@ -79,34 +84,29 @@ def two_site_element(bra: MPS, ket: MPS, E, F, b: int, G1: np.ndarray,
 
 def boundary_insertions(problem, bra: MPS, ket: MPS, l: int, dux, duy, duzz):
     """Accumulate every dO contribution at boundary l (1-based, 0..M):
-    pair (b_{l+1}, a_l)."""
+    pair (b_{l+1}, a_l).  Slice s is U_s = post Z pre (oracle/gates.py)."""
     N, M, dt = problem.N, problem.M, problem.dt
     E, F = environments(bra, ket)
     rho = transitions(bra, ket, E, F)
-    if l >= 1:                                   # outer half of slice l
+    if l >= 1:                                   # outer factor of slice l
         s = l - 1
+        post = gates.slice_post(problem, s)
         for j in range(N):
-            R = gates.half_rotation(problem.ux[s, j], problem.uy[s, j], dt)
-            dx, dy = gates.half_rotation_derivs(problem.ux[s, j],
-                                                problem.uy[s, j], dt)
-            dux[s, j] += np.sum((dx @ R.conj().T) * rho[j])
-            duy[s, j] += np.sum((dy @ R.conj().T) * rho[j])
+            _, P, _, (dx, dy) = gates.site_factors(problem, s, j)
+            dux[s, j] += np.sum((dx @ P.conj().T) * rho[j])
+            duy[s, j] += np.sum((dy @ P.conj().T) * rho[j])
         for b in range(N - 1):
             if not problem.zz_mask[b]:
                 continue
-            R1 = gates.half_rotation(problem.ux[s, b], problem.uy[s, b], dt)
-            R2 = gates.half_rotation(problem.ux[s, b + 1], problem.uy[s, b + 1], dt)
-            W1 = R1 @ gates.Z @ R1.conj().T
-            W2 = R2 @ gates.Z @ R2.conj().T
+            W1 = post[b] @ gates.Z @ post[b].conj().T
+            W2 = post[b + 1] @ gates.Z @ post[b + 1].conj().T
             duzz[s, b] += -1j * dt * two_site_element(bra, ket, E, F, b, W1, W2)
-    if l <= M - 1:                               # inner half of slice l+1
+    if l <= M - 1 and gates.order(problem) == 2:  # inner factor of slice l+1
         s = l
         for j in range(N):
-            R = gates.half_rotation(problem.ux[s, j], problem.uy[s, j], dt)
-            dx, dy = gates.half_rotation_derivs(problem.ux[s, j],
-                                                problem.uy[s, j], dt)
-            dux[s, j] += np.sum((R.conj().T @ dx) * rho[j])
-            duy[s, j] += np.sum((R.conj().T @ dy) * rho[j])
+            Q, _, (dx, dy), _ = gates.site_factors(problem, s, j)
+            dux[s, j] += np.sum((Q.conj().T @ dx) * rho[j])
+            duy[s, j] += np.sum((Q.conj().T @ dy) * rho[j])
 
 
 def trajectory(problem, k: int, r: int, chi: Optional[int] = None,

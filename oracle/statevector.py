@@ -54,15 +54,16 @@ def zz_diagonal(phis: np.ndarray, N: int) -> np.ndarray:
 
 
 def strang_states(problem, k: int, psi0: np.ndarray):
+    """States after every slice of the dense circuit U_l = post Z pre (the
+    split of ``problem.order``, second order by default)."""
     N, M, dt = problem.N, problem.M, problem.dt
     c = gates.couplings(problem, k)
     out = [psi0.copy()]
     psi = psi0.copy()
     for l in range(M):
-        R = gates.slice_rotations(problem, l)
-        psi = apply_all_sites(psi, N, R)
+        psi = apply_all_sites(psi, N, gates.slice_pre(problem, l))
         psi = zz_diagonal(dt * c[l], N) * psi
-        psi = apply_all_sites(psi, N, R)
+        psi = apply_all_sites(psi, N, gates.slice_post(problem, l))
         out.append(psi)
     return out
 
@@ -93,7 +94,7 @@ def exact_final(problem, k: int, psi0: np.ndarray) -> np.ndarray:
 
 
 def adjoint_gradient(problem, k: int, psi0: np.ndarray, target: np.ndarray):
-    """(O, dux, duy, duzz) of the dense Strang circuit."""
+    """(O, dux, duy, duzz) of the dense circuit (second or first order)."""
     N, M, dt = problem.N, problem.M, problem.dt
     c = gates.couplings(problem, k)
     a = strang_states(problem, k, psi0)
@@ -102,38 +103,36 @@ def adjoint_gradient(problem, k: int, psi0: np.ndarray, target: np.ndarray):
     duy = np.zeros((M, N), np.complex128)
     duzz = np.zeros((M, N - 1), np.complex128)
     z = zvalues(N)
+    dag = lambda G: np.conj(np.transpose(G, (0, 2, 1)))
     b = target.copy()                                   # b_{M+1}
     for l in range(M, -1, -1):
         al = a[l]
         if l >= 1:
             s = l - 1
             for j in range(N):
-                R = gates.half_rotation(problem.ux[s, j], problem.uy[s, j], dt)
-                dx, dy = gates.half_rotation_derivs(problem.ux[s, j], problem.uy[s, j], dt)
-                dux[s, j] += np.vdot(b, apply_local(al, N, j, dx @ R.conj().T))
-                duy[s, j] += np.vdot(b, apply_local(al, N, j, dy @ R.conj().T))
-            R = gates.slice_rotations(problem, s)
+                _, P, _, (dx, dy) = gates.site_factors(problem, s, j)
+                dux[s, j] += np.vdot(b, apply_local(al, N, j, dx @ P.conj().T))
+                duy[s, j] += np.vdot(b, apply_local(al, N, j, dy @ P.conj().T))
+            post = gates.slice_post(problem, s)
             for bd in range(N - 1):
                 if not problem.zz_mask[bd]:
                     continue
-                # R (Z Z) R^dagger on the bond, applied as R . ZZ . R^dagger.
-                v = apply_local(al, N, bd, R[bd].conj().T)
-                v = apply_local(v, N, bd + 1, R[bd + 1].conj().T)
+                # post (Z Z) post^dagger on the bond
+                v = apply_local(al, N, bd, post[bd].conj().T)
+                v = apply_local(v, N, bd + 1, post[bd + 1].conj().T)
                 v = z[:, bd] * z[:, bd + 1] * v
-                v = apply_local(v, N, bd, R[bd])
-                v = apply_local(v, N, bd + 1, R[bd + 1])
+                v = apply_local(v, N, bd, post[bd])
+                v = apply_local(v, N, bd + 1, post[bd + 1])
                 duzz[s, bd] += -1j * dt * np.vdot(b, v)
-        if l <= M - 1:
+        if l <= M - 1 and gates.order(problem) == 2:
             s = l
             for j in range(N):
-                R = gates.half_rotation(problem.ux[s, j], problem.uy[s, j], dt)
-                dx, dy = gates.half_rotation_derivs(problem.ux[s, j], problem.uy[s, j], dt)
-                dux[s, j] += np.vdot(b, apply_local(al, N, j, R.conj().T @ dx))
-                duy[s, j] += np.vdot(b, apply_local(al, N, j, R.conj().T @ dy))
+                Q, _, (dx, dy), _ = gates.site_factors(problem, s, j)
+                dux[s, j] += np.vdot(b, apply_local(al, N, j, Q.conj().T @ dx))
+                duy[s, j] += np.vdot(b, apply_local(al, N, j, Q.conj().T @ dy))
         if l >= 1:
             s = l - 1
-            Rh = np.conj(np.transpose(gates.slice_rotations(problem, s), (0, 2, 1)))
-            b = apply_all_sites(b, N, Rh)
+            b = apply_all_sites(b, N, dag(gates.slice_post(problem, s)))
             b = np.conj(zz_diagonal(dt * c[s], N)) * b
-            b = apply_all_sites(b, N, Rh)
+            b = apply_all_sites(b, N, dag(gates.slice_pre(problem, s)))
     return O, dux, duy, duzz

@@ -1,11 +1,12 @@
 """TEBD with SVD truncation (oracle; test infrastructure only).
 
-One slice of the time grid (Sec. II, Eq. 4, taken second order):
+One slice of the time grid (Sec. II, Eq. 4):
 
-    a_l = R_l . trunc[ Z_l . (R_l a_{l-1}) ]
+    a_l = post_l . trunc[ Z_l . (pre_l a_{l-1}) ]
 
-R_l is the product of the single-site half rotations, Z_l the layer of ZZ
-phases.  Z_l is applied bond by bond in a sweep; after each bond the two-site
+pre_l = post_l = R_l, the single-site half rotations, in the second-order
+split; pre_l = I and post_l = X_l Y_l in the paper's first-order split
+(oracle/gates.py).  Z_l is the layer of ZZ phases.  Z_l is applied bond by bond in a sweep; after each bond the two-site
 tensor is split by an SVD and compressed to at most chi singular values (the
 compression to a maximum bond size after every step, Sec. II).  Every bond is
 split, also where its phase is zero, so the truncation is uniform.
@@ -101,24 +102,23 @@ def forward_slice(problem, mps: MPS, l: int, k: int, chi: Optional[int] = None,
                   stats=None) -> MPS:
     """a_l from a_{l-1}; ``l`` is 0-based (slice l+1 of the time grid)."""
     chi = problem.chi if chi is None else chi
-    R = gates.slice_rotations(problem, l)
     phis = problem.dt * gates.couplings(problem, k)[l]
     ltr = (l + 1) % 2 == 1
-    a = rotation_layer(mps, R)
+    a = rotation_layer(mps, gates.slice_pre(problem, l))
     a = zz_layer(a, phis, ltr, chi, problem.eps, problem.renormalize, stats)
-    return rotation_layer(a, R)
+    return rotation_layer(a, gates.slice_post(problem, l))
 
 
 def backward_slice(problem, mps: MPS, l: int, k: int, chi: Optional[int] = None,
                    stats=None) -> MPS:
     """b_l = U_l^dagger b_{l+1} (with truncation); ``l`` is 0-based."""
     chi = problem.chi if chi is None else chi
-    Rh = np.conj(np.transpose(gates.slice_rotations(problem, l), (0, 2, 1)))
+    dag = lambda G: np.conj(np.transpose(G, (0, 2, 1)))
     phis = problem.dt * gates.couplings(problem, k)[l]
     ltr = (problem.M - (l + 1)) % 2 == 0
-    b = rotation_layer(mps, Rh)
+    b = rotation_layer(mps, dag(gates.slice_post(problem, l)))
     b = zz_layer(b, -phis, ltr, chi, problem.eps, problem.renormalize, stats)
-    return rotation_layer(b, Rh)
+    return rotation_layer(b, dag(gates.slice_pre(problem, l)))
 
 
 def evolve(problem, mps: MPS, k: int, l_begin: int = 0,

@@ -56,6 +56,7 @@ class Problem:
     targets: List[List[np.ndarray]]  # R target MPS, each N tensors (Dl,2,Dr)
     task: str = "x"
     name: str = ""
+    order: int = 2          # Trotter split: 2 (R Z R) or 1 (the paper's X Y Z)
 
     @property
     def dt(self) -> float:
@@ -250,7 +251,7 @@ def make_problem(name: Optional[str] = None, *, task: Optional[str] = None,
                  sigma: Optional[float] = None, seed: Optional[int] = None,
                  eps: float = 1e-12, renormalize: bool = True,
                  controls: str = "uniform", amp: float = 1.0,
-                 crosstalk: float = 1.0) -> Problem:
+                 crosstalk: float = 1.0, order: int = 2) -> Problem:
     """Build a seeded synthetic problem.
 
     ``name`` selects one of ``CONFIGS`` (keyword arguments override it).
@@ -258,7 +259,9 @@ def make_problem(name: Optional[str] = None, *, task: Optional[str] = None,
     ``"pi_pulse"`` puts the global pi pulse u^x = pi/T on every site and adds
     U(-amp, amp) to all amplitudes (a near-optimal X-gate pulse, so that F is
     O(1) even at N = 50); ``"zero"`` sets every control to 0.
-    ``crosstalk`` scales the drawn J (0 disables the noise).
+    ``crosstalk`` scales the drawn J (0 disables the noise).  ``order`` picks
+    the Trotter split of a slice (2: second order; 1: the paper's first-order
+    X Y Z product).
     The seed is split with ``SeedSequence(seed).spawn(3)`` into the streams for
     controls, crosstalk and inputs.
     """
@@ -305,7 +308,7 @@ def make_problem(name: Optional[str] = None, *, task: Optional[str] = None,
     return Problem(N=N, M=M, T=float(T), chi=int(chi), eps=float(eps),
                    renormalize=bool(renormalize), ux=ux, uy=uy, uzz=uzz,
                    zz_mask=zz_mask, xt_mask=xt_mask, J=J, inputs=inputs,
-                   targets=targets, task=task, name=name or task)
+                   targets=targets, task=task, name=name or task, order=int(order))
 
 
 # Request mix of the serving workload: N in {10, 20, 30, 50}, chi in
