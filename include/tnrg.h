@@ -9,8 +9,10 @@
  *     + xt_mask_b J_b  (Sec. III, Eqs. 8-9, ZZ part of the crosstalk);
  *   - piecewise-constant controls on M slices of length dt, each slice
  *     applied as the second-order split U_l = R_l Z_l R_l with
- *     R_l = exp(-i dt/2 sum_j h_j), Z_l = exp(-i dt sum_b c_b Z_b Z_{b+1})
- *     (Sec. II, Eq. 4);
+ *     R_l = exp(-i dt/2 sum_j h_j), Z_l = exp(-i dt sum_b c_b Z_b Z_{b+1}),
+ *     or (split_order = 1) as the first-order product U_l = X_l Y_l Z_l of
+ *     Sec. II, Eq. 4 with X_l = exp(-i dt sum_j u^x_j X_j / 2) and
+ *     Y_l = exp(-i dt sum_j u^y_j Y_j / 2);
  *   - the state is an MPS (Sec. II), the ZZ layer is applied by a bond sweep
  *     with an SVD after every bond, compressed to at most chi singular values:
  *     keep k = max(1, min(chi, #{sigma_i >= trunc_eps * sigma_1})) and, with
@@ -18,7 +20,7 @@
  *   - objective: F = 1/(K R) sum_{k,r} |<T_r|psi_kr(T)>|^2 over K crosstalk
  *     samples and R input states (Sec. II, Eq. 7);
  *   - gradient: the adjoint sweep of App. A (Eqs. A1-A2), with the exact
- *     insertion operators of the second-order slice.
+ *     insertion operators of the chosen split.
  *
  * Conventions
  *   - Sites j = 0..N-1, bond b couples (b, b+1); |0> is the Z = +1 state.
@@ -89,6 +91,7 @@ typedef struct {
   int32_t profile;        /* 1: record per-phase clock ticks (tnrg_status) */
   const uint8_t *zz_mask; /* host [N-1]: bond carries the control u^zz */
   const uint8_t *xt_mask; /* host [N-1]: bond carries the crosstalk J */
+  int32_t split_order;    /* 2 (or 0): U_l = R Z R; 1: U_l = X Y Z (Sec. II Eq. 4) */
 } tnrg_model;
 
 /*

@@ -98,6 +98,7 @@ struct ModelDev {
   int renorm;
   int max_sweeps;
   int profile;      // 1: accumulate phase clock ticks into the stats
+  int order;        // Trotter split: 2 (R Z R) or 1 (X Y Z)
   uint64_t zzm[4];  // bit b: bond b carries u^zz
   uint64_t xtm[4];  // bit b: bond b carries crosstalk J
 };

@@ -807,9 +807,19 @@ __device__ __forceinline__ void slice_sweep(Ctx& C, const c2* src, const int* sr
   const sLayout& L = *C.L;
   for (int b = C.tid; b <= N; b += C.nt) C.sdims[b] = src_dims[b];
   __syncthreads();
-  auto gate = [&](int j) {
-    M22 g = m22_load(gate_ptr(gates, N, l, j));
-    return dag ? m22_dag(g) : g;
+  // U_l = post Z pre with post the table entry (R, or X Y in the first-order
+  // split) and pre = post (second order) or I (first order); the adjoint
+  // slice applies post^dag when a site is loaded and pre^dag when it is final
+  const bool first = C.md.order == 1;
+  M22 eye;
+  eye.m[0] = cmk(1.0, 0.0); eye.m[1] = cmk(0.0, 0.0); eye.m[2] = cmk(0.0, 0.0); eye.m[3] = cmk(1.0, 0.0);
+  auto gload = [&](int j) {
+    const M22 g = m22_load(gate_ptr(gates, N, l, j));
+    return dag ? m22_dag(g) : (first ? eye : g);
+  };
+  auto gfin = [&](int j) {
+    const M22 g = m22_load(gate_ptr(gates, N, l, j));
+    return dag ? (first ? eye : m22_dag(g)) : g;
   };
   auto phase = [&](int b) {
     double c = 0.0;
@@ -818,35 +828,35 @@ __device__ __forceinline__ void slice_sweep(Ctx& C, const c2* src, const int* sr
     return sign * C.md.dt * c;
   };
   if (ltr) {
-    load_site(C, C.LC, src + L.off[0], 1, C.sdims[1], L.cap[1], gate(0));
+    load_site(C, C.LC, src + L.off[0], 1, C.sdims[1], L.cap[1], gload(0));
     __syncthreads();
     for (int b = 0; b < N - 1; ++b) {
       const int dl = C.sdims[b], dm = C.sdims[b + 1], dr = C.sdims[b + 2];
       long long tl = ph_now(C);
-      load_site(C, C.LO, src + L.off[b + 1], dm, dr, L.cap[b + 2], gate(b + 1));
+      load_site(C, C.LO, src + L.off[b + 1], dm, dr, L.cap[b + 2], gload(b + 1));
       __syncthreads();
       ph_add(C, kPhLoad, tl);
       const int k = bond_split(C, C.LC, C.LO, dl, dm, dr, phase(b), true,
-                               dst + L.off[b], L.cap[b + 1], gate(b), L.cap[b + 1]);
+                               dst + L.off[b], L.cap[b + 1], gfin(b), L.cap[b + 1]);
       if (C.tid == 0) C.sdims[b + 1] = k;
       __syncthreads();
     }
-    store_site(C, dst + L.off[N - 1], C.LC, C.sdims[N - 1], 1, L.cap[N], gate(N - 1));
+    store_site(C, dst + L.off[N - 1], C.LC, C.sdims[N - 1], 1, L.cap[N], gfin(N - 1));
   } else {
-    load_site(C, C.LC, src + L.off[N - 1], C.sdims[N - 1], 1, L.cap[N], gate(N - 1));
+    load_site(C, C.LC, src + L.off[N - 1], C.sdims[N - 1], 1, L.cap[N], gload(N - 1));
     __syncthreads();
     for (int b = N - 2; b >= 0; --b) {
       const int dl = C.sdims[b], dm = C.sdims[b + 1], dr = C.sdims[b + 2];
       long long tl = ph_now(C);
-      load_site(C, C.LO, src + L.off[b], dl, dm, L.cap[b + 1], gate(b));
+      load_site(C, C.LO, src + L.off[b], dl, dm, L.cap[b + 1], gload(b));
       __syncthreads();
       ph_add(C, kPhLoad, tl);
       const int k = bond_split(C, C.LO, C.LC, dl, dm, dr, phase(b), false,
-                               dst + L.off[b + 1], L.cap[b + 2], gate(b + 1), L.cap[b + 1]);
+                               dst + L.off[b + 1], L.cap[b + 2], gfin(b + 1), L.cap[b + 1]);
       if (C.tid == 0) C.sdims[b + 1] = k;
       __syncthreads();
     }
-    store_site(C, dst + L.off[0], C.LC, 1, C.sdims[1], L.cap[1], gate(0));
+    store_site(C, dst + L.off[0], C.LC, 1, C.sdims[1], L.cap[1], gfin(0));
   }
   __syncthreads();
   for (int b = C.tid; b <= N; b += C.nt) dst_dims[b] = C.sdims[b];

@@ -42,11 +42,36 @@ __device__ __forceinline__ void half_rotation_f_g(double a, double r, double* f,
   }
 }
 
-__global__ void k_gates(int M, int N, double dt, const double* __restrict__ ux,
+__global__ void k_gates(int M, int N, double dt, int order, const double* __restrict__ ux,
                         const double* __restrict__ uy, c2* __restrict__ gates) {
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= M * N) return;
   const double x = ux[idx], y = uy[idx];
+  if (order == 1) {
+    // first-order split: the drive factor of the slice is G = Xr Yr with
+    // Xr = exp(-i dt x X/2), Yr = exp(-i dt y Y/2); stored as G, dG/dux =
+    // (-i dt/2 X) G and dG/duy = Xr (-i dt/2 Y) Yr
+    double sx, cx, sy, cy;
+    sincos(0.5 * dt * x, &sx, &cx);
+    sincos(0.5 * dt * y, &sy, &cy);
+    M22 Xr, Yr, Xh, Yh;
+    Xr.m[0] = cmk(cx, 0.0); Xr.m[1] = cmk(0.0, -sx); Xr.m[2] = cmk(0.0, -sx); Xr.m[3] = cmk(cx, 0.0);
+    Yr.m[0] = cmk(cy, 0.0); Yr.m[1] = cmk(-sy, 0.0); Yr.m[2] = cmk(sy, 0.0); Yr.m[3] = cmk(cy, 0.0);
+    const double h = -0.5 * dt;
+    // -i dt/2 X and -i dt/2 Y
+    Xh.m[0] = cmk(0.0, 0.0); Xh.m[1] = cmk(0.0, h); Xh.m[2] = cmk(0.0, h); Xh.m[3] = cmk(0.0, 0.0);
+    Yh.m[0] = cmk(0.0, 0.0); Yh.m[1] = cmk(h, 0.0); Yh.m[2] = cmk(-h, 0.0); Yh.m[3] = cmk(0.0, 0.0);
+    const M22 G = m22_mul(Xr, Yr);
+    const M22 dGx = m22_mul(Xh, G);
+    const M22 dGy = m22_mul(m22_mul(Xr, Yh), Yr);
+    c2* o = gates + (size_t)idx * 12;
+    for (int q = 0; q < 4; ++q) {
+      o[q] = G.m[q];
+      o[4 + q] = dGx.m[q];
+      o[8 + q] = dGy.m[q];
+    }
+    return;
+  }
   const double a = 0.25 * dt;
   const double r = sqrt(x * x + y * y);
   double f, g;
@@ -256,6 +281,8 @@ int check_model(const tnrg_model* md, ModelDev* out) {
   if (!(md->trunc_eps >= 0.0) || !isfinite(md->trunc_eps))
     return fail(TNRG_EINVAL, "trunc_eps must be finite and >= 0");
   if (md->max_sweeps < 0) return fail(TNRG_EINVAL, "max_sweeps < 0");
+  if (md->split_order != 0 && md->split_order != 1 && md->split_order != 2)
+    return fail(TNRG_EINVAL, "split_order = %d must be 0, 1 or 2", md->split_order);
   if (!md->zz_mask || !md->xt_mask) return fail(TNRG_EINVAL, "bond masks must be host arrays");
   ModelDev d;
   memset(&d, 0, sizeof d);
@@ -267,6 +294,7 @@ int check_model(const tnrg_model* md, ModelDev* out) {
   d.renorm = md->renormalize ? 1 : 0;
   d.max_sweeps = md->max_sweeps > 0 ? md->max_sweeps : 40;
   d.profile = md->profile ? 1 : 0;
+  d.order = md->split_order == 1 ? 1 : 2;
   for (int b = 0; b < md->n - 1; ++b) {
     if (md->zz_mask[b]) d.zzm[b >> 6] |= 1ull << (b & 63);
     if (md->xt_mask[b]) d.xtm[b >> 6] |= 1ull << (b & 63);
@@ -366,7 +394,9 @@ int default_dcap(const tnrg_model* md) {
 int launch_gates(const tnrg_model* md, const double* ux, const double* uy, c2* gates,
                  hipStream_t s) {
   const int n = md->m * md->n;
-  hipLaunchKernelGGL(k_gates, dim3((n + 255) / 256), dim3(256), 0, s, md->m, md->n, md->dt, ux, uy,
+  const int order = md->split_order == 1 ? 1 : 2;
+  hipLaunchKernelGGL(k_gates, dim3((n + 255) / 256), dim3(256), 0, s, md->m, md->n, md->dt, order,
+                     ux, uy,
                      gates);
   return TNRG_OK;
 }
@@ -619,7 +649,7 @@ int grape_launch(int mode, const tnrg_model* md, const double* ux, const double*
   {
     Fnv f;
     f.add(md->n), f.add(md->m), f.add(md->dt), f.add(md->chi), f.add(md->trunc_eps);
-    f.add(md->renormalize), f.add(d.max_sweeps);
+    f.add(md->renormalize), f.add(d.max_sweeps), f.add(d.order);
     for (int b = 0; b + 1 < md->n; ++b) f.add(md->zz_mask[b]), f.add(md->xt_mask[b]);
     f.add(ux), f.add(uy), f.add(uzz), f.add(J), f.add(K), f.add(R), f.add(cap), f.add(cs);
     f.add(inputs->data), f.add(targets->data), f.add(ws);

@@ -52,7 +52,8 @@ class _Model(ctypes.Structure):
                 ("renormalize", ctypes.c_int32), ("max_sweeps", ctypes.c_int32),
                 ("profile", ctypes.c_int32),
                 ("zz_mask", ctypes.POINTER(ctypes.c_uint8)),
-                ("xt_mask", ctypes.POINTER(ctypes.c_uint8))]
+                ("xt_mask", ctypes.POINTER(ctypes.c_uint8)),
+                ("split_order", ctypes.c_int32)]
 
 
 class _Batch(ctypes.Structure):
@@ -164,6 +165,7 @@ class Model:
     profile: bool = False
     zz_mask: Optional[np.ndarray] = None
     xt_mask: Optional[np.ndarray] = None
+    order: int = 2  # Trotter split: 2 (R Z R) or 1 (the first-order X Y Z)
 
     def c(self) -> _Model:
         zz = np.ascontiguousarray(self.zz_mask if self.zz_mask is not None
@@ -174,7 +176,7 @@ class Model:
                    1 if self.renormalize else 0, int(self.max_sweeps),
                    1 if self.profile else 0,
                    zz.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
-                   xt.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)))
+                   xt.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), int(self.order))
         m._keep = (zz, xt)
         return m
 
@@ -182,7 +184,7 @@ class Model:
     def from_problem(cls, p, **kw) -> "Model":
         return cls(N=p.N, M=p.M, dt=p.dt, chi=p.chi, eps=p.eps,
                    renormalize=p.renormalize, zz_mask=p.zz_mask,
-                   xt_mask=p.xt_mask, **kw)
+                   xt_mask=p.xt_mask, order=getattr(p, "order", 2), **kw)
 
 
 def bond_cap(N: int, dcap: int, b: int) -> int:

@@ -208,3 +208,46 @@ def test_large_bonds_match_oracle(P, N, M, T, chi):
     O = res["overlaps"].cpu().numpy()
     for (k, r), Or in ref["overlaps"].items():
         assert abs(O[k, r] - Or) <= 1e-10 * max(abs(Or), 1e-6)
+
+
+# The paper's first-order split U_l = X_l Y_l Z_l (Sec. II, Eq. 4) with the
+# insertions of App. A, against the oracle's first-order path.
+@pytest.mark.parametrize("task,N,M,chi,sigma,seed", [
+    ("x", 8, 12, 16, 0.02, 23), ("cnot", 8, 10, 16, 0.3, 23), ("ghz", 8, 9, 16, 0.3, 23),
+    ("cnot", 10, 8, 4, 0.5, 25)])
+def test_first_order_grape_matches_oracle(P, task, N, M, chi, sigma, seed):
+    p = W.make_problem(task=task, N=N, M=M, T=M * 0.3, chi=chi, K=3, R=2, sigma=sigma, seed=seed,
+                       order=1)
+    say(f"first-order grape: task={task} N={N} M={M} chi={chi}")
+    for k in range(p.K):
+        for r in range(p.R):
+            assert min(cut_gaps(p, k, r)) >= 1e-8
+    res = _grape_case(P, p)
+    ref = og.fidelity_grad(p, details=True)
+    F = float(res["F"].cpu())
+    assert abs(F - ref["F"]) <= 1e-10 * abs(ref["F"]) + 1e-15
+    for name in ("g_ux", "g_uy", "g_uzz"):
+        g = res[name].cpu().numpy()
+        gr = ref[name]
+        scale = max(np.max(np.abs(gr)), 1e-300)
+        assert np.max(np.abs(g - gr)) <= 1e-10 * scale + 1e-15, (name, np.max(np.abs(g - gr)), scale)
+    O = res["overlaps"].cpu().numpy()
+    for (k, r), Or in ref["overlaps"].items():
+        assert abs(O[k, r] - Or) <= 1e-10 * max(abs(Or), 1e-6)
+
+
+@pytest.mark.parametrize("adjoint", [False, True])
+def test_first_order_evolve_matches_oracle(P, adjoint):
+    p = W.make_problem(task="cnot", N=8, M=5, T=2.0, chi=16, K=3, R=1, sigma=0.3, seed=17,
+                       order=1)
+    say(f"first-order evolve: adjoint={adjoint}")
+    d = device_problem(p)
+    states = [omps.product_state(p.inputs[0]) for _ in range(p.K)]
+    if adjoint:
+        states = [omps.right_canonicalize(p.targets[0]) for _ in range(p.K)]
+    batch = P.MPSBatch.from_mps(states, dcap=16)
+    P.mps_evolve(d["model"], d["ux"], d["uy"], d["uzz"], d["J"], batch, adjoint=adjoint)
+    got = batch.to_mps()
+    for k in range(p.K):
+        ref = otebd.evolve(p, states[k], k, adjoint=adjoint)
+        assert np.max(np.abs(omps.to_dense(got[k]) - omps.to_dense(ref))) < 1e-12
