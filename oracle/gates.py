@@ -15,10 +15,20 @@ product of the same three kinds of factor, U = X Y Z with
 ``problem.order`` (2, the default, or 1) selects the split.  Either way a
 slice is U = post . Z . pre with per-site 2x2 factors: pre = post = R
 (second order) or pre = I, post = X Y (first order).
+
+With the paper's Heisenberg-type crosstalk (Sec. III, Eq. 9) the two-site
+factor of bond b is the 4x4 exponential
+
+    G_b = exp(-i dt (J^x XX + J^y YY + c_b ZZ)),   c_b = u^zz + J^z,
+
+and Z is the ordered product of the G_b over the bonds in the order the
+slice's sweep visits them (the terms of neighbouring bonds do not commute;
+oracle/tebd.py fixes the order).
 """
 from __future__ import annotations
 
 import numpy as np
+import scipy.linalg
 
 I2 = np.eye(2, dtype=np.complex128)
 X = np.array([[0, 1], [1, 0]], dtype=np.complex128)
@@ -70,10 +80,42 @@ def zz_phase(phi: float) -> np.ndarray:
     return np.exp(-1j * phi * np.outer(ZVALS, ZVALS))
 
 
+def heisenberg(problem) -> bool:
+    return getattr(problem, "xt_model", "zz") == "heisenberg"
+
+
 def couplings(problem, k: int) -> np.ndarray:
-    """c[l, b] = zz_mask_b u^zz[l, b] + xt_mask_b J[k, b], shape (M, N-1)."""
+    """ZZ coefficient c[l, b] = zz_mask_b u^zz[l, b] + xt_mask_b J^z[k, b],
+    shape (M, N-1) (J^z is J[k, b] in the ZZ model)."""
+    Jz = problem.J[k][:, 2] if heisenberg(problem) else problem.J[k]
     return (problem.zz_mask[None, :] * problem.uzz
-            + problem.xt_mask[None, :] * problem.J[k][None, :])
+            + problem.xt_mask[None, :] * Jz[None, :])
+
+
+XX = np.kron(X, X)
+YY = np.kron(Y, Y)
+ZZ = np.kron(Z, Z)
+
+
+def bond_hamiltonian(jx: float, jy: float, cz: float) -> np.ndarray:
+    """jx XX + jy YY + cz ZZ, 4x4 over (s_b, s_{b+1}) with s_b the major index."""
+    return jx * XX + jy * YY + cz * ZZ
+
+
+def bond_gate(jx: float, jy: float, cz: float, dt: float) -> np.ndarray:
+    """exp(-i dt (jx XX + jy YY + cz ZZ)) as a (2, 2, 2, 2) array
+    [s, t, s', t'] (out site b, out site b+1, in site b, in site b+1)."""
+    return scipy.linalg.expm(-1j * dt * bond_hamiltonian(jx, jy, cz)).reshape(2, 2, 2, 2)
+
+
+def bond_gates(problem, k: int, l: int):
+    """G_b of slice l (0-based), noise sample k, for every bond (Heisenberg
+    crosstalk model)."""
+    c = couplings(problem, k)[l]
+    J = problem.J[k]
+    xm = problem.xt_mask
+    return [bond_gate(xm[b] * J[b, 0], xm[b] * J[b, 1], c[b], problem.dt)
+            for b in range(problem.N - 1)]
 
 
 def slice_rotations(problem, l: int) -> np.ndarray:

@@ -24,6 +24,21 @@ factor and the positions follow from differentiating the slice).  All matrix
 elements at one boundary come from one pass of left/right transfer
 environments.  dF = 1/(K R) sum 2 Re(conj(O_kr) dO_kr), with the final forward
 overlap O_kr for every boundary.
+
+With Heisenberg crosstalk the bond gates of one slice do not commute, so
+Z Z_b cannot be moved to the slice boundary.  For the sweep order of
+oracle/tebd.py (bond b visited after the bonds before it in the sweep),
+d/du^zz_b of the ordered product is the product with -i dt Z_b Z_{b+1}
+placed right after G_b (Z Z commutes with its own bond gate), and its matrix
+element is
+
+    -i dt <beta_b | Z_b Z_{b+1} | alpha_b>,
+
+alpha_b the forward working state of the two-site layer just after bond b is
+updated, beta_b the backward working state of the same slice just before
+bond b is updated (the backward slice undoes the bonds in the opposite
+order, so beta_b has undone exactly the gates that follow G_b).  Both are the
+truncated states the two sweeps produce.
 """
 from __future__ import annotations
 
@@ -32,7 +47,7 @@ from typing import Optional
 import numpy as np
 
 from . import gates, tebd
-from .mps import MPS, overlap, product_state, right_canonicalize
+from .mps import MPS, copy, overlap, product_state, right_canonicalize
 
 
 def environments(bra: MPS, ket: MPS):
@@ -96,7 +111,7 @@ def boundary_insertions(problem, bra: MPS, ket: MPS, l: int, dux, duy, duzz):
             dux[s, j] += np.sum((dx @ P.conj().T) * rho[j])
             duy[s, j] += np.sum((dy @ P.conj().T) * rho[j])
         for b in range(N - 1):
-            if not problem.zz_mask[b]:
+            if not problem.zz_mask[b] or gates.heisenberg(problem):
                 continue
             W1 = post[b] @ gates.Z @ post[b].conj().T
             W2 = post[b + 1] @ gates.Z @ post[b + 1].conj().T
@@ -127,8 +142,32 @@ def trajectory(problem, k: int, r: int, chi: Optional[int] = None,
     for l in range(M, -1, -1):
         boundary_insertions(problem, b, a[l], l, dux, duy, duzz)
         if l >= 1:
-            b = tebd.backward_slice(problem, b, l - 1, k, chi, stats)
+            if gates.heisenberg(problem) and problem.zz_mask.any():
+                b = _backward_with_zz(problem, a[l - 1], b, l - 1, k, chi, stats, duzz)
+            else:
+                b = tebd.backward_slice(problem, b, l - 1, k, chi, stats)
     return O, dux, duy, duzz
+
+
+def _zz_on_bond(state: MPS, b: int) -> MPS:
+    out = copy(state)
+    out[b] = out[b] * gates.ZVALS[None, :, None]
+    out[b + 1] = out[b + 1] * gates.ZVALS[None, :, None]
+    return out
+
+
+def _backward_with_zz(problem, a_prev: MPS, b_next: MPS, s: int, k: int, chi, stats, duzz):
+    """Backward slice s with the mid-sweep u^zz insertions (Heisenberg
+    crosstalk): alpha_b from re-running forward slice s on a_{s}, beta_b from
+    the backward sweep itself."""
+    alpha = {}
+    tebd.forward_slice(problem, a_prev, s, k, chi,
+                       after=lambda bd, st: alpha.__setitem__(bd, copy(st)))
+
+    def before(bd, st):
+        if problem.zz_mask[bd]:
+            duzz[s, bd] += -1j * problem.dt * overlap(st, _zz_on_bond(alpha[bd], bd))
+    return tebd.backward_slice(problem, b_next, s, k, chi, stats, before=before)
 
 
 def fidelity_grad(problem, chi: Optional[int] = None, trajectories=None,

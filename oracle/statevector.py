@@ -1,10 +1,12 @@
 """Dense state-vector references (oracle; test infrastructure only, N <= ~12).
 
 * ``strang_states``: the same second-order circuit R Z R per slice as the MPS
-  code, applied to a 2^N vector, no truncation.
+  code, applied to a 2^N vector, no truncation (with Heisenberg crosstalk, Z
+  is the product of the 4x4 bond gates in the slice's sweep order).
 * ``exact_states``: piecewise-constant exact propagation
   psi_l = expm(-i H_l dt) psi_{l-1} with H_l = sum_j (ux X + uy Y)_j / 2 +
-  sum_b c_b Z_b Z_{b+1} (Sec. II, Eq. 1 with Sec. III, Eq. 8), for the
+  sum_b c_b Z_b Z_{b+1} (Sec. II, Eq. 1 with Sec. III, Eq. 8; plus
+  J^x XX + J^y YY on each bond with Heisenberg crosstalk, Eq. 9), for the
   second-order error check.
 * ``adjoint_gradient``: dO/du of the dense Strang circuit from dense forward
   and backward vectors and the same insertion operators as the MPS adjoint.
@@ -30,6 +32,23 @@ def kron_vec(vecs) -> np.ndarray:
 def apply_local(psi: np.ndarray, N: int, j: int, G: np.ndarray) -> np.ndarray:
     t = psi.reshape((2 ** j, 2, 2 ** (N - j - 1)))
     return np.einsum("st,atb->asb", G, t).reshape(-1)
+
+
+def apply_two(psi: np.ndarray, N: int, b: int, G: np.ndarray) -> np.ndarray:
+    """Apply the (2, 2, 2, 2) gate G[s, t, s', t'] to sites (b, b+1)."""
+    t = psi.reshape((2 ** b, 2, 2, 2 ** (N - b - 2)))
+    return np.einsum("stuv,auvc->astc", G, t).reshape(-1)
+
+
+def bond_layer(psi: np.ndarray, problem, k: int, l: int) -> np.ndarray:
+    """Heisenberg two-site layer of forward slice l: the bond gates in the
+    slice's sweep order, the first visited bond acting first."""
+    N = problem.N
+    G = gates.bond_gates(problem, k, l)
+    ltr = (problem.M - 1 - l) % 2 == 1
+    for b in (range(N - 1) if ltr else range(N - 2, -1, -1)):
+        psi = apply_two(psi, N, b, G[b])
+    return psi
 
 
 def apply_all_sites(psi: np.ndarray, N: int, Gs) -> np.ndarray:
@@ -62,7 +81,10 @@ def strang_states(problem, k: int, psi0: np.ndarray):
     psi = psi0.copy()
     for l in range(M):
         psi = apply_all_sites(psi, N, gates.slice_pre(problem, l))
-        psi = zz_diagonal(dt * c[l], N) * psi
+        if gates.heisenberg(problem):
+            psi = bond_layer(psi, problem, k, l)
+        else:
+            psi = zz_diagonal(dt * c[l], N) * psi
         psi = apply_all_sites(psi, N, gates.slice_post(problem, l))
         out.append(psi)
     return out
@@ -77,6 +99,12 @@ def hamiltonian(problem, k: int, l: int) -> scipy.sparse.csr_matrix:
     for b in range(N - 1):
         diag += c[b] * z[:, b] * z[:, b + 1]
     H = scipy.sparse.diags(diag.astype(np.complex128)).tocsr()
+    if gates.heisenberg(problem):
+        J = problem.J[k]
+        for b in range(N - 1):
+            op = problem.xt_mask[b] * (J[b, 0] * gates.XX + J[b, 1] * gates.YY)
+            H = H + scipy.sparse.kron(scipy.sparse.identity(2 ** b),
+                                      scipy.sparse.kron(op, scipy.sparse.identity(2 ** (N - b - 2))))
     for j in range(N):
         loc = 0.5 * (problem.ux[l, j] * gates.X + problem.uy[l, j] * gates.Y)
         op = scipy.sparse.kron(scipy.sparse.identity(2 ** j),
@@ -94,7 +122,10 @@ def exact_final(problem, k: int, psi0: np.ndarray) -> np.ndarray:
 
 
 def adjoint_gradient(problem, k: int, psi0: np.ndarray, target: np.ndarray):
-    """(O, dux, duy, duzz) of the dense circuit (second or first order)."""
+    """(O, dux, duy, duzz) of the dense circuit (second or first order, ZZ
+    crosstalk)."""
+    if gates.heisenberg(problem):
+        raise NotImplementedError("dense adjoint of the ZZ crosstalk model only")
     N, M, dt = problem.N, problem.M, problem.dt
     c = gates.couplings(problem, k)
     a = strang_states(problem, k, psi0)

@@ -6,17 +6,26 @@ One slice of the time grid (Sec. II, Eq. 4):
 
 pre_l = post_l = R_l, the single-site half rotations, in the second-order
 split; pre_l = I and post_l = X_l Y_l in the paper's first-order split
-(oracle/gates.py).  Z_l is the layer of ZZ phases.  Z_l is applied bond by bond in a sweep; after each bond the two-site
-tensor is split by an SVD and compressed to at most chi singular values (the
-compression to a maximum bond size after every step, Sec. II).  Every bond is
-split, also where its phase is zero, so the truncation is uniform.
+(oracle/gates.py).  Z_l is the two-site layer: ZZ phases in the ZZ crosstalk
+model, the 4x4 bond exponentials G_b with Heisenberg crosstalk.  Z_l is
+applied bond by bond in a sweep; after each bond the two-site tensor is split
+by an SVD and compressed to at most chi singular values (the compression to a
+maximum bond size after every step, Sec. II).  Every bond is split, also where
+its gate is the identity, so the truncation is uniform.
 
 Canonical form: an MPS entering a left-to-right sweep has its orthogonality
 centre on site 0 and every other site right-isometric; the sweep leaves the
 centre on site N-1 (sites 0..N-2 left-isometric), and a right-to-left sweep
 mirrors this.  Slices alternate direction: forward slice l (1-based) sweeps
-left to right when l is odd; backward slice l sweeps left to right when M - l
-is even.
+left to right when M - l is odd, backward slice l when M - l is even, so the
+two sweeps of one slice always run in opposite directions and the last
+forward slice ends with the centre on site 0, where the right-canonical
+target starts the backward pass.  The Heisenberg bond gates of neighbouring
+bonds do not commute, so their product is taken in the order of the forward
+sweep (the bond visited first acts first) and the backward slice, sweeping
+the other way, applies the exact adjoint of that product.  Two consecutive
+forward slices visit the bonds in mirror order, a symmetric product, which
+keeps the splitting of the bond terms at second order.
 
 Truncation rule: singular values sorted in descending order, keep
     k = max(1, min(chi, #{i : sigma_i >= eps * sigma_1}))
@@ -78,19 +87,60 @@ def split_two_site(theta: np.ndarray, chi: int, eps: float, renormalize: bool,
     return left.reshape(Dl, 2, k), right.reshape(k, 2, Dr)
 
 
-def zz_layer(mps: MPS, phis: np.ndarray, left_to_right: bool, chi: int,
-             eps: float, renormalize: bool,
-             stats: Optional[List[Dict]] = None) -> MPS:
-    """Apply prod_b exp(-i phis[b] Z_b Z_{b+1}) by a truncated bond sweep."""
+def bond_sweep(mps: MPS, gate, left_to_right: bool, chi: int, eps: float,
+               renormalize: bool, stats: Optional[List[Dict]] = None,
+               before=None, after=None) -> MPS:
+    """Apply the two-site gates bond by bond in sweep order, each followed by
+    a truncated split.  ``gate(b, theta)`` returns the gated theta
+    (Dl, 2, 2, Dr).  ``before(b, state)`` / ``after(b, state)`` see the
+    working MPS just before / just after bond b is updated."""
     out = copy(mps)
     N = len(out)
     order = range(N - 1) if left_to_right else range(N - 2, -1, -1)
     for b in order:
+        if before is not None:
+            before(b, out)
         theta = np.einsum("asb,btc->astc", out[b], out[b + 1])
-        theta = theta * gates.zz_phase(phis[b])[None, :, :, None]
+        theta = gate(b, theta)
         out[b], out[b + 1] = split_two_site(theta, chi, eps, renormalize,
                                             left_to_right, stats)
+        if after is not None:
+            after(b, out)
     return out
+
+
+def zz_layer(mps: MPS, phis: np.ndarray, left_to_right: bool, chi: int,
+             eps: float, renormalize: bool,
+             stats: Optional[List[Dict]] = None) -> MPS:
+    """Apply prod_b exp(-i phis[b] Z_b Z_{b+1}) by a truncated bond sweep."""
+    return bond_sweep(mps, lambda b, th: th * gates.zz_phase(phis[b])[None, :, :, None],
+                      left_to_right, chi, eps, renormalize, stats)
+
+
+def _apply4(G: np.ndarray, theta: np.ndarray) -> np.ndarray:
+    """theta'[a, s, t, c] = sum G[s, t, s', t'] theta[a, s', t', c]."""
+    return np.einsum("stuv,auvc->astc", G, theta)
+
+
+def forward_ltr(problem, l: int) -> bool:
+    """Sweep direction of forward slice l (0-based): left to right when
+    M - (l + 1) is odd."""
+    return (problem.M - 1 - l) % 2 == 1
+
+
+def _layer(problem, mps: MPS, l: int, k: int, ltr: bool, adjoint: bool, chi: int,
+           stats, before=None, after=None) -> MPS:
+    if gates.heisenberg(problem):
+        G = gates.bond_gates(problem, k, l)
+        if adjoint:   # (G_b)^dagger: swap (out, in) pairs and conjugate
+            G = [np.conj(np.transpose(g, (2, 3, 0, 1))) for g in G]
+        return bond_sweep(mps, lambda b, th: _apply4(G[b], th), ltr, chi, problem.eps,
+                          problem.renormalize, stats, before, after)
+    if before is not None or after is not None:
+        raise ValueError("sweep hooks are only used with Heisenberg crosstalk")
+    phis = problem.dt * gates.couplings(problem, k)[l]
+    return zz_layer(mps, -phis if adjoint else phis, ltr, chi, problem.eps,
+                    problem.renormalize, stats)
 
 
 def rotation_layer(mps: MPS, G: np.ndarray) -> MPS:
@@ -99,25 +149,25 @@ def rotation_layer(mps: MPS, G: np.ndarray) -> MPS:
 
 
 def forward_slice(problem, mps: MPS, l: int, k: int, chi: Optional[int] = None,
-                  stats=None) -> MPS:
-    """a_l from a_{l-1}; ``l`` is 0-based (slice l+1 of the time grid)."""
+                  stats=None, after=None) -> MPS:
+    """a_l from a_{l-1}; ``l`` is 0-based (slice l+1 of the time grid).
+    ``after(b, state)`` (Heisenberg crosstalk only) sees the two-site layer's
+    working MPS after each bond update."""
     chi = problem.chi if chi is None else chi
-    phis = problem.dt * gates.couplings(problem, k)[l]
-    ltr = (l + 1) % 2 == 1
     a = rotation_layer(mps, gates.slice_pre(problem, l))
-    a = zz_layer(a, phis, ltr, chi, problem.eps, problem.renormalize, stats)
+    a = _layer(problem, a, l, k, forward_ltr(problem, l), False, chi, stats, after=after)
     return rotation_layer(a, gates.slice_post(problem, l))
 
 
 def backward_slice(problem, mps: MPS, l: int, k: int, chi: Optional[int] = None,
-                   stats=None) -> MPS:
-    """b_l = U_l^dagger b_{l+1} (with truncation); ``l`` is 0-based."""
+                   stats=None, before=None) -> MPS:
+    """b_l = U_l^dagger b_{l+1} (with truncation); ``l`` is 0-based.
+    ``before(b, state)`` (Heisenberg crosstalk only) sees the working MPS
+    before each bond update."""
     chi = problem.chi if chi is None else chi
     dag = lambda G: np.conj(np.transpose(G, (0, 2, 1)))
-    phis = problem.dt * gates.couplings(problem, k)[l]
-    ltr = (problem.M - (l + 1)) % 2 == 0
     b = rotation_layer(mps, dag(gates.slice_post(problem, l)))
-    b = zz_layer(b, -phis, ltr, chi, problem.eps, problem.renormalize, stats)
+    b = _layer(problem, b, l, k, not forward_ltr(problem, l), True, chi, stats, before=before)
     return rotation_layer(b, dag(gates.slice_pre(problem, l)))
 
 

@@ -63,12 +63,15 @@ def test_norm_and_unitarity_without_renormalisation():
     assert abs(mps.overlap(a0, back) - 1.0) < 1e-12
 
 
-def test_sweeps_leave_canonical_form():
-    p = _problem(N=8, M=3, sigma=0.5)
+@pytest.mark.parametrize("M", [3, 4])
+def test_sweeps_leave_canonical_form(M):
+    p = _problem(N=8, M=M, sigma=0.5)
     a = mps.product_state(p.inputs[0])
-    a1 = tebd.forward_slice(p, a, 0, 0)          # left to right: centre at N-1
+    # the last forward slice sweeps right to left, the one before it left to right
+    assert not tebd.forward_ltr(p, M - 1) and tebd.forward_ltr(p, M - 2)
+    a1 = tebd.forward_slice(p, a, M - 2, 0)      # left to right: centre at N-1
     assert all(mps.is_left_isometric(A) for A in a1[:-1])
-    a2 = tebd.forward_slice(p, a1, 1, 0)         # right to left: centre at 0
+    a2 = tebd.forward_slice(p, a1, M - 1, 0)     # right to left: centre at 0
     assert all(mps.is_right_isometric(A) for A in a2[1:])
     assert abs(np.linalg.norm(a2[0]) - 1.0) < 1e-13
 

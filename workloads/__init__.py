@@ -16,10 +16,13 @@ Conventions shared by every consumer
   ``uzz[l, b]`` (shape (M, N-1)); slice l = 0..M-1 here is slice l+1 of the
   paper's 1-based time grid (Sec. II, Eq. 4).
 * ``zz_mask[b]`` marks bonds that carry the controllable coupling u^zz,
-  ``xt_mask[b]`` marks bonds that carry the static crosstalk J (Sec. III,
-  Eqs. 8-9, ZZ part only).
-* ``J[k, b]`` is the crosstalk strength of noise sample k on bond b, static in
-  time; trajectory t of a batch is (k, r) = (t // R, t % R).
+  ``xt_mask[b]`` marks bonds that carry the static crosstalk (Sec. III,
+  Eqs. 8-9).
+* Crosstalk model ``xt_model``: ``"zz"`` keeps the J_j Z_j Z_{j+1} part of
+  Eq. 9 and ``J[k, b]`` is its strength for noise sample k on bond b;
+  ``"heisenberg"`` is the full Eq. 9, J^x XX + J^y YY + J^z ZZ on every bond,
+  and ``J[k, b, :]`` holds (J^x, J^y, J^z).  Static in time; trajectory t of
+  a batch is (k, r) = (t // R, t % R).
 * Targets are returned right-canonical (every site right-isometric, the first
   site carrying the norm, which is 1).
 """
@@ -51,12 +54,13 @@ class Problem:
     uzz: np.ndarray         # (M, N-1) float64
     zz_mask: np.ndarray     # (N-1,) uint8
     xt_mask: np.ndarray     # (N-1,) uint8
-    J: np.ndarray           # (K, N-1) float64, zero where xt_mask == 0
+    J: np.ndarray           # (K, N-1) or, Heisenberg, (K, N-1, 3) float64; 0 off xt_mask
     inputs: np.ndarray      # (R, N, 2) complex128 product-state qubits
     targets: List[List[np.ndarray]]  # R target MPS, each N tensors (Dl,2,Dr)
     task: str = "x"
     name: str = ""
     order: int = 2          # Trotter split: 2 (R Z R) or 1 (the paper's X Y Z)
+    xt_model: str = "zz"    # crosstalk: "zz" or "heisenberg" (XX + YY + ZZ)
 
     @property
     def dt(self) -> float:
@@ -251,7 +255,8 @@ def make_problem(name: Optional[str] = None, *, task: Optional[str] = None,
                  sigma: Optional[float] = None, seed: Optional[int] = None,
                  eps: float = 1e-12, renormalize: bool = True,
                  controls: str = "uniform", amp: float = 1.0,
-                 crosstalk: float = 1.0, order: int = 2) -> Problem:
+                 crosstalk: float = 1.0, order: int = 2, xt_model: str = "zz",
+                 delta_j: float = 0.05) -> Problem:
     """Build a seeded synthetic problem.
 
     ``name`` selects one of ``CONFIGS`` (keyword arguments override it).
@@ -261,7 +266,10 @@ def make_problem(name: Optional[str] = None, *, task: Optional[str] = None,
     O(1) even at N = 50); ``"zero"`` sets every control to 0.
     ``crosstalk`` scales the drawn J (0 disables the noise).  ``order`` picks
     the Trotter split of a slice (2: second order; 1: the paper's first-order
-    X Y Z product).
+    X Y Z product).  ``xt_model="heisenberg"`` draws the paper's noise model
+    instead of the ZZ one: J^x, J^y, J^z independent and uniform in
+    [-delta_j, delta_j] on every bond (Sec. II; Sec. III, Eq. 9); ``sigma`` is
+    then unused.
     The seed is split with ``SeedSequence(seed).spawn(3)`` into the streams for
     controls, crosstalk and inputs.
     """
@@ -280,6 +288,10 @@ def make_problem(name: Optional[str] = None, *, task: Optional[str] = None,
     ss = np.random.SeedSequence(seed).spawn(3)
     rc, rj, ri = (np.random.default_rng(s) for s in ss)
     zz_mask, xt_mask = _masks(task, N)
+    if xt_model not in ("zz", "heisenberg"):
+        raise ValueError(f"unknown crosstalk model {xt_model!r}")
+    if xt_model == "heisenberg":
+        xt_mask = np.ones(N - 1, np.uint8)   # Eq. 9 sums over every bond
 
     if controls == "uniform":
         ux = rc.uniform(-amp, amp, (M, N))
@@ -297,7 +309,10 @@ def make_problem(name: Optional[str] = None, *, task: Optional[str] = None,
         raise ValueError(controls)
     uzz = uzz * zz_mask[None, :]
 
-    J = rj.normal(0.0, sigma, (K, N - 1)) * crosstalk * xt_mask[None, :]
+    if xt_model == "heisenberg":
+        J = rj.uniform(-delta_j, delta_j, (K, N - 1, 3)) * crosstalk * xt_mask[None, :, None]
+    else:
+        J = rj.normal(0.0, sigma, (K, N - 1)) * crosstalk * xt_mask[None, :]
 
     if task in ("ghz", "heisenberg"):
         inputs = np.zeros((R, N, 2), np.complex128)
@@ -308,7 +323,8 @@ def make_problem(name: Optional[str] = None, *, task: Optional[str] = None,
     return Problem(N=N, M=M, T=float(T), chi=int(chi), eps=float(eps),
                    renormalize=bool(renormalize), ux=ux, uy=uy, uzz=uzz,
                    zz_mask=zz_mask, xt_mask=xt_mask, J=J, inputs=inputs,
-                   targets=targets, task=task, name=name or task, order=int(order))
+                   targets=targets, task=task, name=name or task, order=int(order),
+                   xt_model=xt_model)
 
 
 # Request mix of the serving workload: N in {10, 20, 30, 50}, chi in
