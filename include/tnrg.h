@@ -92,6 +92,10 @@ typedef struct {
   const uint8_t *zz_mask; /* host [N-1]: bond carries the control u^zz */
   const uint8_t *xt_mask; /* host [N-1]: bond carries the crosstalk J */
   int32_t split_order;    /* 2 (or 0): U_l = R Z R; 1: U_l = X Y Z (Sec. II Eq. 4) */
+  int32_t xt_model;       /* crosstalk (Sec. III Eq. 9): 0 = J Z Z (J is [.][N-1]);
+                             1 = J^x XX + J^y YY + J^z ZZ (J is [.][N-1][3] holding
+                             (J^x, J^y, J^z)); the two-site layer is then the
+                             product of the bond exponentials in sweep order */
 } tnrg_model;
 
 /*
@@ -118,15 +122,17 @@ int64_t tnrg_mps_traj_elems(int32_t n_sites, int32_t dcap);
 /*
  * mps_evolve -- apply slices l_begin..l_end-1 of the time grid (Sec. II,
  * Eq. 4, second order; TEBD with SVD truncation) to every MPS of psi, in
- * place.  adjoint = 0: psi <- U_{l_end-1} ... U_{l_begin} psi, the ZZ sweep of
- * slice l going left to right when l is even.  adjoint = 1:
+ * place.  adjoint = 0: psi <- U_{l_end-1} ... U_{l_begin} psi, the two-site
+ * sweep of slice l going left to right when M - 1 - l is odd (with
+ * xt_model = 1 the bond visited first acts first).  adjoint = 1:
  * psi <- U_{l_begin}^dag ... U_{l_end-1}^dag psi, the sweep of slice l going
- * left to right when M - 1 - l is even.  The MPS entering a left-to-right
+ * left to right when M - 1 - l is even, the exact adjoint of slice l.  The MPS entering a left-to-right
  * sweep must have its orthogonality centre on site 0 (sites 1..N-1
  * right-isometric), and on site N-1 for a right-to-left sweep; product states
  * qualify for both.
  *   ux, uy, uzz: device controls [M][N], [M][N], [M][N-1].
- *   J: device [psi->n_traj][N-1], the crosstalk of each trajectory.
+ *   J: device [psi->n_traj][N-1] (xt_model 0) or [psi->n_traj][N-1][3]
+ *      (xt_model 1), the crosstalk of each trajectory.
  *   ws: device workspace of at least mps_evolve_workspace_bytes() bytes.
  */
 size_t mps_evolve_workspace_bytes(const tnrg_model *md, int32_t n_traj,
@@ -153,8 +159,12 @@ int mps_overlap(const tnrg_mps_batch *bra, const tnrg_mps_batch *ket,
  * times R inputs, in one persistent launch with one workgroup per
  * trajectory.  Forward states are checkpointed every ckpt_stride slices
  * (0 selects ceil(sqrt(M))) and recomputed segment by segment during the
- * adjoint sweep.
- *   J: device [K][N-1].
+ * adjoint sweep.  With xt_model = 1 the u^zz derivative of bond b is taken
+ * inside the sweep, between the forward state just after bond b and the
+ * backward state just before it (App. A for the ordered bond product); the
+ * adjoint then also re-runs each forward slice once to recover the forward
+ * states inside it, and the workspace holds ckpt_stride more MPS.
+ *   J: device [K][N-1] (xt_model 0) or [K][N-1][3] (xt_model 1).
  *   inputs: R MPS (each canonical with centre on site 0; product states are).
  *   targets: R MPS, right-canonical with unit norm (sites 1..N-1
  *            right-isometric).

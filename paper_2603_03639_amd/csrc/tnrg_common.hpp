@@ -99,9 +99,36 @@ struct ModelDev {
   int max_sweeps;
   int profile;      // 1: accumulate phase clock ticks into the stats
   int order;        // Trotter split: 2 (R Z R) or 1 (X Y Z)
+  int heis;         // 1: Heisenberg crosstalk J^x XX + J^y YY + J^z ZZ, J row [N-1][3]
+  int hgrad;        // heis and some bond carries u^zz: mid-sweep u^zz insertions
+  int zz_lo, zz_hi; // lowest and highest bond with u^zz (N-1, -1 when none)
   uint64_t zzm[4];  // bit b: bond b carries u^zz
   uint64_t xtm[4];  // bit b: bond b carries crosstalk J
 };
+// Two-site gate exp(-i t (jx XX + jy YY + cz ZZ)) of one bond (Sec. III,
+// Eq. 9).  The three terms commute and couple |s s'> only with
+// |1-s 1-s'>, so the gate is block diagonal.  On {|00>, |11>} (block 0)
+// ZZ = +1 and XX + YY acts as (jx - jy) sigma_x, so the block is
+// e^{-i t cz} (cos(a) I - i sin(a) sigma_x) with a = t (jx - jy); on
+// {|01>, |10>} (block 1) ZZ = -1 and the block is e^{+i t cz} times the same
+// form with a = t (jx + jy).  d = diagonal, o = off-diagonal entry of each
+// block.  With jx = jy = 0 it is the ZZ phase (o = 0 exactly).
+struct BondGate {
+  c2 d[2], o[2];
+};
+__device__ __forceinline__ BondGate bond_gate(double t, double jx, double jy, double cz) {
+  BondGate g;
+  const double z = t * cz, a0 = t * (jx - jy), a1 = t * (jx + jy);
+  const double cp = cos(z), sp = sin(z);
+  const c2 p0 = cmk(cp, -sp), p1 = cmk(cp, sp);
+  const double c0 = cos(a0), s0 = sin(a0), c1 = cos(a1), s1 = sin(a1);
+  g.d[0] = cmk(p0.x * c0, p0.y * c0);
+  g.o[0] = cmk(p0.y * s0, -p0.x * s0);  // p0 (-i s0)
+  g.d[1] = cmk(p1.x * c1, p1.y * c1);
+  g.o[1] = cmk(p1.y * s1, -p1.x * s1);
+  return g;
+}
+
 __device__ __forceinline__ bool bit(const uint64_t* m, int b) {
   // every word is read and the choice is made on values, never on an
   // address, so the mask words (and the context holding them) stay in

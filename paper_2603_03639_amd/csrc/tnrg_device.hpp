@@ -666,15 +666,15 @@ __device__ __forceinline__ void store_site(Ctx& C, c2* site, const sc2* src, int
 // ----------------------------------------------------------------------------
 // Two-site update of one bond (Sec. II: apply the two-qubit gate, split by an
 // SVD, compress).  Lt (dl,2,dm) and Rt (dm,2,dr) are packed in LDS; the gate
-// is the ZZ phase exp(-i phi z_s z_s').
+// bg is the bond exponential (the ZZ phase, or the Heisenberg bond gate).
 //   ltr: left factor U (left-isometric) is written to `iso` (site b, capacity
 //        row stride iso_capr) after the gate Gfin, the centre diag(s) V^dag
 //        (k,2,dr) is left in LC.
 //   rtl: right factor V^dag is written to `iso` (site b+1), the centre
 //        U diag(s) (dl,2,k) is left in LC.
-// Returns k, the new bond dimension.
+// iso may be null (nothing written).  Returns k, the new bond dimension.
 __device__ __forceinline__ int bond_split(Ctx& C, const sc2* Lt, const sc2* Rt, int dl, int dm, int dr,
-                          double phi, bool ltr, c2* iso, int iso_capr, const M22& Gfin,
+                          const BondGate& bg, bool ltr, c2* iso, int iso_capr, const M22& Gfin,
                           int capk) {
   long long t0 = ph_now(C);
   const int len = ltr ? 2 * dl : 2 * dr;
@@ -682,29 +682,45 @@ __device__ __forceinline__ int bond_split(Ctx& C, const sc2* Lt, const sc2* Rt, 
   const int ldx = pow2_at_least(len) + 1;
   sc2* X = C.X;
   c2* X0 = C.X0;
-  const double cp = cos(phi), sp = sin(phi);
-  const c2 ph_same = cmk(cp, -sp);  // exp(-i phi)   (z_s z_s' = +1)
-  const c2 ph_diff = cmk(cp, sp);   // exp(+i phi)   (z_s z_s' = -1)
-  // theta[(a,s),(s',c)] = P[s][s'] sum_b Lt[a,s,b] Rt[b,s',c]
-  const int nth = 4 * dl * dr;
-  for (DivWalk w(C.tid, C.nt, 2 * dr); w.idx < nth; w.next()) {
-    const int row = w.q;
-    const int col = w.r;
-    const int s = row & 1;
-    const int s2 = col >= dr ? 1 : 0;
-    const int c = col - s2 * dr;
-    const sc2* lp = Lt + row * dm;
-    const sc2* rp = Rt + s2 * dr + c;
-    c2 acc = cmk(0.0, 0.0);
+  const bool offd = C.md.heis;
+  // theta[(a,s),(s',c)] = sum_b Lt[a,s,b] Rt[b,s',c], then the gate, which
+  // couples (s,s') only with (1-s,1-s'): one item makes the pair
+  // (0,s') / (1,1-s') of row pair a and column c
+  const int npair = 2 * dl * dr;
+  for (DivWalk w(C.tid, C.nt, 2 * dr); w.idx < npair; w.next()) {
+    const int a = w.q;
+    const int col0 = w.r;
+    const int s2 = col0 >= dr ? 1 : 0;
+    const int c = col0 - s2 * dr;
+    const int col1 = col0 + (s2 ? -dr : dr);
+    const int row0 = 2 * a, row1 = 2 * a + 1;
+    const sc2* lp0 = Lt + row0 * dm;
+    const sc2* lp1 = Lt + row1 * dm;
+    const sc2* rp0 = Rt + s2 * dr + c;
+    const sc2* rp1 = Rt + (1 - s2) * dr + c;
+    c2 t0v = cmk(0.0, 0.0), t1v = cmk(0.0, 0.0);
 #pragma unroll 4
-    for (int b = 0; b < dm; ++b) acc = cfma(lp[b], rp[b * 2 * dr], acc);
-    acc = cmul(acc, s == s2 ? ph_same : ph_diff);
+    for (int b = 0; b < dm; ++b) {
+      t0v = cfma(lp0[b], rp0[b * 2 * dr], t0v);
+      t1v = cfma(lp1[b], rp1[b * 2 * dr], t1v);
+    }
+    const c2 d = s2 ? bg.d[1] : bg.d[0];
+    c2 v0 = cmul(t0v, d), v1 = cmul(t1v, d);
+    if (offd) {
+      const c2 o = s2 ? bg.o[1] : bg.o[0];
+      v0 = cfma(o, t1v, v0);
+      v1 = cfma(o, t0v, v1);
+    }
     if (ltr) {
-      X[col * ldx + row] = acc;
-      X0[col * ldx + row] = acc;
+      X[col0 * ldx + row0] = v0;
+      X0[col0 * ldx + row0] = v0;
+      X[col1 * ldx + row1] = v1;
+      X0[col1 * ldx + row1] = v1;
     } else {
-      X[row * ldx + col] = cconj(acc);
-      X0[row * ldx + col] = cconj(acc);
+      X[row0 * ldx + col0] = cconj(v0);
+      X0[row0 * ldx + col0] = cconj(v0);
+      X[row1 * ldx + col1] = cconj(v1);
+      X0[row1 * ldx + col1] = cconj(v1);
     }
   }
   __syncthreads();
@@ -762,7 +778,8 @@ __device__ __forceinline__ int bond_split(Ctx& C, const sc2* Lt, const sc2* Rt, 
       C.LC[c * k + i] = cscale(cconj(acc), inv);
   }
   // isometry to HBM with the finishing gate
-  if (ltr) {
+  if (!iso) {
+  } else if (ltr) {
     // site b: (dl, 2, k), A[a,s,i] = sum_t G[s][t] Q_i[a*2+t]
     const int n = dl * 2 * k;
     for (DivWalk w(C.tid, C.nt, 2 * k); w.idx < n; w.next()) {
@@ -796,15 +813,190 @@ __device__ __forceinline__ const c2* gate_ptr(const c2* gates, int N, int l, int
   return gates + ((size_t)l * N + j) * 12;
 }
 
-// One slice of the ZZ layer with the two half rotations fused: every site is
-// rotated by G when it is first loaded and again when it is final for this
-// slice, so src -> dst realises G . trunc[Z . (G psi)] (Sec. II, Eq. 4, second
-// order).  For an adjoint slice G = R^dag and phi -> -phi.  src may equal dst.
+// ----------------------------------------------------------------------------
+// Gradient accumulator of one trajectory: 2 Re(conj(O) dO) into g, and dO
+// itself when requested.
+struct GradOut {
+  double* g;  // [nctrl] 2 Re(conj O dO)
+  c2* dO;     // [nctrl] or nullptr
+  c2 O;
+};
+
+// Extra work of the adjoint's sweeps with Heisenberg crosstalk, where the
+// u^zz derivative sits inside the ordered bond product (App. A): for the
+// forward sweep of slice l, d/du^zz_b places -i dt Z_b Z_{b+1} right after
+// G_b, and its matrix element pairs the forward working state just after
+// bond b (alpha_b) with the backward working state just before bond b
+// (beta_b), the backward slice undoing the bonds in the opposite order.
+//   kSweepCentres: the forward slice re-run from its input a_l, which also
+//     keeps the centre left after every bond update in `cen` (MPS layout;
+//     after bond b: site b+1 sweeping left to right, site b right to left);
+//     with a null dst it writes nothing else.  With the left-isometric sites (taken from
+//     a_{l+1}, its post factor undone) and the untouched sites of the input
+//     (pre a_l) it spells out alpha_b.
+//   kSweepInsert: the backward slice (beta_b is its working state) adds
+//     -i dt <beta_b| Z_b Z_{b+1} |alpha_b> before each bond b with u^zz.  The
+//     environment on the side the sweep has not reached is the stored one
+//     of <b_{l+1}|a_{l+1}> (site-local factors cancel in it); the one on the
+//     side it has passed is grown bond by bond from the final backward sites
+//     and the input sites of a_l (the pre factor cancels there).
+constexpr int kSweepPlain = 0, kSweepCentres = 1, kSweepInsert = 2;
+struct SweepExtra {
+  c2* cen;           // centres of the forward re-run
+  const c2* a_next;  // a_{l+1} and its dims
+  const int* dn;
+  const c2* a_prev;  // a_l and its dims
+  const int* dp;
+  const c2* envs;    // <b_{l+1}|a_{l+1}>, stride cap^2: left E_j [bra][ket] for a
+                     // right-to-left backward sweep, right F_j [ket][bra] otherwise
+  c2* inc;           // 2 cap^2: the environment grown by the sweep (ping-pong)
+  GradOut* go;
+  size_t gidx;       // gradient index of u^zz (slice l, bond 0)
+};
+
+// <bra| Z_b Z_{b+1} |ket> from sites b, b+1 of each state and the
+// environments on either side:
+//   sum E(z,a) conj(B1[z,s,x]) (G1 A1)[a,s,y] z_s conj(B2[x,t,x']) (G2 A2)[y,t,y'] z_t Rr(x',y')
+// B1 (bl,2,bm), A1 (al,2,am), B2 (bm,2,br), A2 (am,2,ar); T(i,s,j) at
+// T[(i*2+s)*ld + j]; E(z,a) = Ep[z*es0 + a*es1], Rr(x',y') = Rp[x'*rs0 + y'*rs1].
+// Scratch: C.X.  Returns the value to every thread.
+template <class PE, class PB1, class PA1, class PB2, class PA2, class PR>
+__device__ __forceinline__ c2 zz_sandwich(Ctx& C, PE Ep, int es0, int es1, PB1 B1, int ldb1, PA1 A1,
+                                          int lda1, const M22& G1, PB2 B2, int ldb2, PA2 A2, int lda2,
+                                          const M22& G2, PR Rp, int rs0, int rs1, int bl, int al,
+                                          int bm, int am, int br, int ar) {
+  int P2 = 4;
+  while (P2 < 2 * C.cap) P2 <<= 1;
+  const int xs = P2 * (P2 + 1);
+  sc2* P = C.X;                     // P[s][z][y]   2 bl am
+  sc2* Q = C.X + xs - bm * am;      // Q[x][y]      bm am (top of X)
+  sc2* Wt = C.X;                    // W[t][x][y']  2 bm ar (P is dead by then)
+  if (C.tid == 0) C.sstat[5] += 16LL * (bl * am * al + bm * am * bl + bm * ar * am + bm * br * ar);
+  // P[s][z][y] = sum_a E(z,a) (G1 A1)[a,s,y]
+  for (DivWalk w(C.tid, C.nt, am); w.idx < bl * am; w.next()) {
+    const int z = w.q, y = w.r;
+    c2 u0 = cmk(0.0, 0.0), u1 = cmk(0.0, 0.0);
+    for (int a = 0; a < al; ++a) {
+      const c2 e = Ep[z * es0 + a * es1];
+      u0 = cfma(e, A1[(size_t)(a * 2 + 0) * lda1 + y], u0);
+      u1 = cfma(e, A1[(size_t)(a * 2 + 1) * lda1 + y], u1);
+    }
+    P[z * am + y] = m22_row(G1, 0, u0, u1);
+    P[bl * am + z * am + y] = m22_row(G1, 1, u0, u1);
+  }
+  __syncthreads();
+  // Q[x][y] = sum_s z_s sum_z conj(B1[z,s,x]) P[s][z][y]
+  for (DivWalk w(C.tid, C.nt, am); w.idx < bm * am; w.next()) {
+    const int x = w.q, y = w.r;
+    c2 q0 = cmk(0.0, 0.0), q1 = cmk(0.0, 0.0);
+    for (int z = 0; z < bl; ++z) {
+      q0 = cfmac(B1[(size_t)(z * 2 + 0) * ldb1 + x], P[z * am + y], q0);
+      q1 = cfmac(B1[(size_t)(z * 2 + 1) * ldb1 + x], P[bl * am + z * am + y], q1);
+    }
+    Q[x * am + y] = csub(q0, q1);
+  }
+  __syncthreads();
+  // W[t][x][y'] = sum_y Q[x][y] (G2 A2)[y,t,y']
+  for (DivWalk w(C.tid, C.nt, ar); w.idx < bm * ar; w.next()) {
+    const int x = w.q, yp = w.r;
+    c2 u0 = cmk(0.0, 0.0), u1 = cmk(0.0, 0.0);
+    for (int y = 0; y < am; ++y) {
+      const c2 q = Q[x * am + y];
+      u0 = cfma(q, A2[(size_t)(y * 2 + 0) * lda2 + yp], u0);
+      u1 = cfma(q, A2[(size_t)(y * 2 + 1) * lda2 + yp], u1);
+    }
+    Wt[x * ar + yp] = m22_row(G2, 0, u0, u1);
+    Wt[bm * ar + x * ar + yp] = m22_row(G2, 1, u0, u1);
+  }
+  __syncthreads();
+  // sum_{t,x,x'} z_t conj(B2[x,t,x']) sum_y' W[t][x][y'] Rr(x',y')
+  c2 acc[1] = {cmk(0.0, 0.0)};
+  for (DivWalk w(C.tid, C.nt, br); w.idx < 2 * bm * br; w.next()) {
+    const int t = w.q >= bm ? 1 : 0;
+    const int x = w.q - t * bm, xp = w.r;
+    c2 v = cmk(0.0, 0.0);
+    for (int yp = 0; yp < ar; ++yp) v = cfma(Wt[t * bm * ar + x * ar + yp], Rp[xp * rs0 + yp * rs1], v);
+    const c2 bv = B2[(size_t)(x * 2 + t) * ldb2 + xp];
+    const c2 term = cmul(cconj(bv), v);
+    acc[0] = t ? csub(acc[0], term) : cadd(acc[0], term);
+  }
+  block_sum<1>(C, acc);
+  return acc[0];
+}
+
+// Right environment grown by one site: Rn[x][y] = sum_s sum_x' conj(St[x,s,x'])
+// sum_y' Ap[y,s,y'] Ro[x'][y'], St (nx,2,nxo), Ap (ny,2,nyo), Ro (nxo x nyo)
+// and Rn (nx x ny) packed row-major.  Scratch: C.X.
+__device__ __forceinline__ void grow_right(Ctx& C, const c2* St, int lds_, const c2* Ap, int lda,
+                                           const c2* Ro, c2* Rn, int nx, int nxo, int ny, int nyo) {
+  sc2* T = C.X;  // T[s][y][x']
+  if (C.tid == 0) C.sstat[5] += 16LL * (ny * nxo * nyo + nx * ny * nxo);
+  for (DivWalk w(C.tid, C.nt, nxo); w.idx < 2 * ny * nxo; w.next()) {
+    const int s = w.q >= ny ? 1 : 0;
+    const int y = w.q - s * ny, xp = w.r;
+    c2 v = cmk(0.0, 0.0);
+    for (int yp = 0; yp < nyo; ++yp) v = cfma(Ap[(size_t)(y * 2 + s) * lda + yp], Ro[xp * nyo + yp], v);
+    T[(s * ny + y) * nxo + xp] = v;
+  }
+  __syncthreads();
+  for (DivWalk w(C.tid, C.nt, ny); w.idx < nx * ny; w.next()) {
+    const int x = w.q, y = w.r;
+    c2 v = cmk(0.0, 0.0);
+    for (int s = 0; s < 2; ++s)
+      for (int xp = 0; xp < nxo; ++xp)
+        v = cfmac(St[(size_t)(x * 2 + s) * lds_ + xp], T[(s * ny + y) * nxo + xp], v);
+    Rn[x * ny + y] = v;
+  }
+  __syncthreads();
+}
+
+// Left environment grown by one site: Ln[x][y] = sum_s sum_x0 conj(St[x0,s,x])
+// sum_y0 Lo[x0][y0] Ap[y0,s,y], St (nxo,2,nx), Ap (nyo,2,ny), Lo (nxo x nyo),
+// Ln (nx x ny) packed row-major.  Scratch: C.X.
+__device__ __forceinline__ void grow_left(Ctx& C, const c2* St, int lds_, const c2* Ap, int lda,
+                                          const c2* Lo, c2* Ln, int nx, int nxo, int ny, int nyo) {
+  sc2* T = C.X;  // T[s][x0][y]
+  if (C.tid == 0) C.sstat[5] += 16LL * (nxo * ny * nyo + nx * ny * nxo);
+  for (DivWalk w(C.tid, C.nt, ny); w.idx < 2 * nxo * ny; w.next()) {
+    const int s = w.q >= nxo ? 1 : 0;
+    const int x0 = w.q - s * nxo, y = w.r;
+    c2 v = cmk(0.0, 0.0);
+    for (int y0 = 0; y0 < nyo; ++y0) v = cfma(Lo[x0 * nyo + y0], Ap[(size_t)(y0 * 2 + s) * lda + y], v);
+    T[(s * nxo + x0) * ny + y] = v;
+  }
+  __syncthreads();
+  for (DivWalk w(C.tid, C.nt, ny); w.idx < nx * ny; w.next()) {
+    const int x = w.q, y = w.r;
+    c2 v = cmk(0.0, 0.0);
+    for (int s = 0; s < 2; ++s)
+      for (int x0 = 0; x0 < nxo; ++x0)
+        v = cfmac(St[(size_t)(x0 * 2 + s) * lds_ + x], T[(s * nxo + x0) * ny + y], v);
+    Ln[x * ny + y] = v;
+  }
+  __syncthreads();
+}
+
+// Centre left in LC (dl, 2, dr packed) to an MPS-layout site (row stride capr).
+__device__ __forceinline__ void save_centre(Ctx& C, c2* site, int dl, int dr, int capr) {
+  for (DivWalk w(C.tid, C.nt, dr); w.idx < 2 * dl * dr; w.next())
+    site[(size_t)w.q * capr + w.r] = C.LC[w.idx];
+}
+
+// One slice of the two-site layer with the two half rotations fused: every
+// site is rotated by G when it is first loaded and again when it is final
+// for this slice, so src -> dst realises G . trunc[Z . (G psi)] (Sec. II,
+// Eq. 4, second order).  Z applies the bond gates in sweep order.  For an
+// adjoint slice G = R^dag and every bond gate is replaced by its adjoint
+// (time t -> -t).  src may equal dst.  kX and ex: the extra work described
+// at SweepExtra (dst and dst_dims may be null with kSweepCentres).
+template <int kX>
 __device__ __forceinline__ void slice_sweep(Ctx& C, const c2* src, const int* src_dims, c2* dst,
                             int* dst_dims, bool ltr, const c2* gates, int l, bool dag,
-                            double sign, const double* uzz, const double* Jrow) {
+                            double sign, const double* uzz, const double* Jrow,
+                            const SweepExtra* ex) {
   const int N = C.md.N;
   const sLayout& L = *C.L;
+  const int cc = C.cap * C.cap;
   for (int b = C.tid; b <= N; b += C.nt) C.sdims[b] = src_dims[b];
   __syncthreads();
   // U_l = post Z pre with post the table entry (R, or X Y in the first-order
@@ -821,14 +1013,32 @@ __device__ __forceinline__ void slice_sweep(Ctx& C, const c2* src, const int* sr
     const M22 g = m22_load(gate_ptr(gates, N, l, j));
     return dag ? (first ? eye : m22_dag(g)) : g;
   };
-  auto phase = [&](int b) {
-    double c = 0.0;
-    if (bit(C.md.zzm, b)) c += uzz[(size_t)l * (N - 1) + b];
-    if (bit(C.md.xtm, b)) c += Jrow[b];
-    return sign * C.md.dt * c;
+  auto bgate = [&](int b) {
+    double cz = 0.0, jx = 0.0, jy = 0.0;
+    if (bit(C.md.zzm, b)) cz += uzz[(size_t)l * (N - 1) + b];
+    if (bit(C.md.xtm, b)) {
+      if (C.md.heis) {
+        jx = Jrow[3 * b];
+        jy = Jrow[3 * b + 1];
+        cz += Jrow[3 * b + 2];
+      } else {
+        cz += Jrow[b];
+      }
+    }
+    return bond_gate(sign * C.md.dt, jx, jy, cz);
   };
+  auto add_zz = [&](int b, c2 val) {
+    if (C.tid == 0) {
+      const c2 v = cmk(C.md.dt * val.y, -C.md.dt * val.x);  // -i dt val
+      const size_t idx = ex->gidx + b;
+      ex->go->g[idx] += 2.0 * (ex->go->O.x * v.x + ex->go->O.y * v.y);
+      if (ex->go->dO) ex->go->dO[idx] = cadd(ex->go->dO[idx], v);
+    }
+  };
+  int cur = 0;  // ping-pong half of ex->inc holding the grown environment
   if (ltr) {
     load_site(C, C.LC, src + L.off[0], 1, C.sdims[1], L.cap[1], gload(0));
+    if (kX == kSweepInsert && C.tid == 0) ex->inc[0] = cmk(1.0, 0.0);
     __syncthreads();
     for (int b = 0; b < N - 1; ++b) {
       const int dl = C.sdims[b], dm = C.sdims[b + 1], dr = C.sdims[b + 2];
@@ -836,14 +1046,31 @@ __device__ __forceinline__ void slice_sweep(Ctx& C, const c2* src, const int* sr
       load_site(C, C.LO, src + L.off[b + 1], dm, dr, L.cap[b + 2], gload(b + 1));
       __syncthreads();
       ph_add(C, kPhLoad, tl);
-      const int k = bond_split(C, C.LC, C.LO, dl, dm, dr, phase(b), true,
-                               dst + L.off[b], L.cap[b + 1], gfin(b), L.cap[b + 1]);
+      if (kX == kSweepInsert && bit(C.md.zzm, b)) {
+        const int* dp = ex->dp;
+        const int* dn = ex->dn;
+        const c2 v = zz_sandwich(C, ex->inc + cur * cc, dp[b], 1, C.LC, dm, ex->cen + L.off[b],
+                                 L.cap[b + 1], eye, C.LO, dr, ex->a_next + L.off[b + 1], L.cap[b + 2],
+                                 gload(b + 1), ex->envs + (size_t)(b + 2) * cc, 1, dr, dl, dp[b], dm,
+                                 dn[b + 1], dr, dn[b + 2]);
+        add_zz(b, v);
+      }
+      const int k = bond_split(C, C.LC, C.LO, dl, dm, dr, bgate(b), true,
+                               dst ? dst + L.off[b] : nullptr, L.cap[b + 1], gfin(b), L.cap[b + 1]);
       if (C.tid == 0) C.sdims[b + 1] = k;
       __syncthreads();
+      if (kX == kSweepCentres) save_centre(C, ex->cen + L.off[b + 1], k, dr, L.cap[b + 2]);
+      if (kX == kSweepInsert && b < C.md.zz_hi) {
+        const int* dp = ex->dp;
+        grow_left(C, dst + L.off[b], L.cap[b + 1], ex->a_prev + L.off[b], L.cap[b + 1],
+                  ex->inc + cur * cc, ex->inc + (1 - cur) * cc, k, dl, dp[b + 1], dp[b]);
+        cur ^= 1;
+      }
     }
-    store_site(C, dst + L.off[N - 1], C.LC, C.sdims[N - 1], 1, L.cap[N], gfin(N - 1));
+    if (dst) store_site(C, dst + L.off[N - 1], C.LC, C.sdims[N - 1], 1, L.cap[N], gfin(N - 1));
   } else {
     load_site(C, C.LC, src + L.off[N - 1], C.sdims[N - 1], 1, L.cap[N], gload(N - 1));
+    if (kX == kSweepInsert && C.tid == 0) ex->inc[0] = cmk(1.0, 0.0);
     __syncthreads();
     for (int b = N - 2; b >= 0; --b) {
       const int dl = C.sdims[b], dm = C.sdims[b + 1], dr = C.sdims[b + 2];
@@ -851,31 +1078,66 @@ __device__ __forceinline__ void slice_sweep(Ctx& C, const c2* src, const int* sr
       load_site(C, C.LO, src + L.off[b], dl, dm, L.cap[b + 1], gload(b));
       __syncthreads();
       ph_add(C, kPhLoad, tl);
-      const int k = bond_split(C, C.LO, C.LC, dl, dm, dr, phase(b), false,
-                               dst + L.off[b + 1], L.cap[b + 2], gfin(b + 1), L.cap[b + 1]);
+      if (kX == kSweepInsert && bit(C.md.zzm, b)) {
+        const int* dp = ex->dp;
+        const int* dn = ex->dn;
+        const c2 v = zz_sandwich(C, ex->envs + (size_t)b * cc, dn[b], 1, C.LO, dm,
+                                 ex->a_next + L.off[b], L.cap[b + 1], gload(b), C.LC, dr,
+                                 ex->cen + L.off[b + 1], L.cap[b + 2], eye, ex->inc + cur * cc,
+                                 dp[b + 2], 1, dl, dn[b], dm, dn[b + 1], dr, dp[b + 2]);
+        add_zz(b, v);
+      }
+      const int k = bond_split(C, C.LO, C.LC, dl, dm, dr, bgate(b), false,
+                               dst ? dst + L.off[b + 1] : nullptr, L.cap[b + 2], gfin(b + 1),
+                               L.cap[b + 1]);
       if (C.tid == 0) C.sdims[b + 1] = k;
       __syncthreads();
+      if (kX == kSweepCentres) save_centre(C, ex->cen + L.off[b], dl, k, L.cap[b + 1]);
+      if (kX == kSweepInsert && b > C.md.zz_lo) {
+        const int* dp = ex->dp;
+        grow_right(C, dst + L.off[b + 1], L.cap[b + 2], ex->a_prev + L.off[b + 1], L.cap[b + 2],
+                   ex->inc + cur * cc, ex->inc + (1 - cur) * cc, k, dr, dp[b + 1], dp[b + 2]);
+        cur ^= 1;
+      }
     }
-    store_site(C, dst + L.off[0], C.LC, 1, C.sdims[1], L.cap[1], gfin(0));
+    if (dst) store_site(C, dst + L.off[0], C.LC, 1, C.sdims[1], L.cap[1], gfin(0));
   }
   __syncthreads();
-  for (int b = C.tid; b <= N; b += C.nt) dst_dims[b] = C.sdims[b];
+  if (dst_dims)
+    for (int b = C.tid; b <= N; b += C.nt) dst_dims[b] = C.sdims[b];
   __syncthreads();
 }
 
-// Forward slice l (0-based): left to right when l is even.
+// Forward slice l (0-based): left to right when M - 1 - l is odd, so the
+// last slice sweeps right to left and every forward slice runs opposite to
+// its adjoint (the bond visited first acts first).
+__device__ __forceinline__ bool forward_ltr(const Ctx& C, int l) { return ((C.md.M - 1 - l) % 2) == 1; }
 __device__ __forceinline__ void forward_slice(Ctx& C, const c2* src, const int* sd, c2* dst,
                                               int* dd, const c2* gates, int l,
                                               const double* uzz, const double* Jrow) {
-  slice_sweep(C, src, sd, dst, dd, (l % 2) == 0, gates, l, false, 1.0, uzz, Jrow);
+  slice_sweep<kSweepPlain>(C, src, sd, dst, dd, forward_ltr(C, l), gates, l, false, 1.0, uzz, Jrow,
+                           nullptr);
+}
+// Forward re-run of slice l keeping the centres (kSweepCentres); dst, dd
+// may be null.
+__device__ __forceinline__ void forward_centres(Ctx& C, const c2* src, const int* sd, c2* dst,
+                                                int* dd, const c2* gates, int l, const double* uzz,
+                                                const double* Jrow, const SweepExtra* ex) {
+  slice_sweep<kSweepCentres>(C, src, sd, dst, dd, forward_ltr(C, l), gates, l, false, 1.0, uzz,
+                             Jrow, ex);
 }
 // Adjoint slice l (0-based): b_l = U_l^dag b_{l+1}; left to right when
-// M - 1 - l is even.
+// M - 1 - l is even.  With ex, the mid-sweep u^zz insertions (kSweepInsert).
 __device__ __forceinline__ void adjoint_slice(Ctx& C, const c2* src, const int* sd, c2* dst,
                                               int* dd, const c2* gates, int l,
-                                              const double* uzz, const double* Jrow) {
-  slice_sweep(C, src, sd, dst, dd, ((C.md.M - 1 - l) % 2) == 0, gates, l, true, -1.0, uzz,
-              Jrow);
+                                              const double* uzz, const double* Jrow,
+                                              const SweepExtra* ex = nullptr) {
+  if (ex)
+    slice_sweep<kSweepInsert>(C, src, sd, dst, dd, !forward_ltr(C, l), gates, l, true, -1.0, uzz,
+                              Jrow, ex);
+  else
+    slice_sweep<kSweepPlain>(C, src, sd, dst, dd, !forward_ltr(C, l), gates, l, true, -1.0, uzz,
+                             Jrow, nullptr);
 }
 
 // Copy one MPS between two capacity layouts (dims must fit the destination).

@@ -133,6 +133,7 @@ struct GrapeArgs {
   long long* stats;
   char* traj_base;
   size_t traj_bytes, slot_bytes, dims_off, off_x0, off_env, off_O, off_g;
+  size_t off_env2;  // mid-sweep u^zz insertions: right envs (N+1) cap^2 + 2 cap^2
   size_t off_big;  // working buffers of the global-scratch variant (capacities above 32)
   c2* overlaps;
   c2* traj_dO;
@@ -283,6 +284,8 @@ int check_model(const tnrg_model* md, ModelDev* out) {
   if (md->max_sweeps < 0) return fail(TNRG_EINVAL, "max_sweeps < 0");
   if (md->split_order != 0 && md->split_order != 1 && md->split_order != 2)
     return fail(TNRG_EINVAL, "split_order = %d must be 0, 1 or 2", md->split_order);
+  if (md->xt_model != 0 && md->xt_model != 1)
+    return fail(TNRG_EINVAL, "xt_model = %d must be 0 or 1", md->xt_model);
   if (!md->zz_mask || !md->xt_mask) return fail(TNRG_EINVAL, "bond masks must be host arrays");
   ModelDev d;
   memset(&d, 0, sizeof d);
@@ -295,10 +298,18 @@ int check_model(const tnrg_model* md, ModelDev* out) {
   d.max_sweeps = md->max_sweeps > 0 ? md->max_sweeps : 40;
   d.profile = md->profile ? 1 : 0;
   d.order = md->split_order == 1 ? 1 : 2;
+  d.heis = md->xt_model == 1 ? 1 : 0;
+  d.zz_lo = md->n - 1;
+  d.zz_hi = -1;
   for (int b = 0; b < md->n - 1; ++b) {
-    if (md->zz_mask[b]) d.zzm[b >> 6] |= 1ull << (b & 63);
+    if (md->zz_mask[b]) {
+      d.zzm[b >> 6] |= 1ull << (b & 63);
+      d.zz_lo = std::min(d.zz_lo, b);
+      d.zz_hi = std::max(d.zz_hi, b);
+    }
     if (md->xt_mask[b]) d.xtm[b >> 6] |= 1ull << (b & 63);
   }
+  d.hgrad = d.heis && d.zz_hi >= 0;
   *out = d;
   return TNRG_OK;
 }
@@ -354,9 +365,19 @@ size_t big_bytes(int cap) { return use_lds(cap) ? 0 : align256(dyn_lds_bytes(cap
 
 struct GrapeLayout {
   int cs, nck, nslots, nctrl, dcap;
-  size_t slot_bytes, dims_off, off_x0, off_env, off_O, off_g, off_big, traj_bytes;
+  size_t slot_bytes, dims_off, off_x0, off_env, off_env2, off_O, off_g, off_big, traj_bytes;
   size_t off_flags, off_stats, off_gates, off_traj, total;
 };
+
+// Heisenberg crosstalk with some u^zz control: the adjoint takes the u^zz
+// derivative inside its sweeps (more workspace: the centres of one segment
+// and two environment buffers).
+bool mid_sweep_zz(const tnrg_model* md) {
+  if (md->xt_model != 1) return false;
+  for (int b = 0; b < md->n - 1; ++b)
+    if (md->zz_mask[b]) return true;
+  return false;
+}
 
 GrapeLayout grape_layout(const tnrg_model* md, int K, int R, int dcap, int cs) {
   GrapeLayout g;
@@ -364,14 +385,16 @@ GrapeLayout grape_layout(const tnrg_model* md, int K, int R, int dcap, int cs) {
   g.dcap = dcap;
   g.cs = cs;
   g.nck = (M + cs - 1) / cs;
-  g.nslots = g.nck + cs + 2;
+  const bool hg = mid_sweep_zz(md);
+  g.nslots = g.nck + cs + 2 + (hg ? cs : 0);
   g.nctrl = 2 * M * N + M * (N - 1);
   const size_t elems = (size_t)site_offset_slow(N, dcap, N);
   g.dims_off = align256(elems * sizeof(c2));
   g.slot_bytes = align256(g.dims_off + (size_t)(N + 1) * sizeof(int));
   g.off_x0 = (size_t)g.nslots * g.slot_bytes;
   g.off_env = g.off_x0 + align256((size_t)x_elems(dcap) * sizeof(c2));
-  g.off_O = g.off_env + align256((size_t)(N + 1) * dcap * dcap * sizeof(c2));
+  g.off_env2 = g.off_env + align256((size_t)(N + 1) * dcap * dcap * sizeof(c2));
+  g.off_O = g.off_env2 + (hg ? align256((size_t)(N + 3) * dcap * dcap * sizeof(c2)) : 0);
   g.off_g = g.off_O + 256;
   g.off_big = align256(g.off_g + (size_t)g.nctrl * sizeof(double));
   g.traj_bytes = g.off_big + big_bytes(dcap);
@@ -640,6 +663,7 @@ int grape_launch(int mode, const tnrg_model* md, const double* ux, const double*
   A.dims_off = G.dims_off;
   A.off_x0 = G.off_x0;
   A.off_env = G.off_env;
+  A.off_env2 = G.off_env2;
   A.off_O = G.off_O;
   A.off_g = G.off_g;
   A.off_big = G.off_big;
@@ -649,7 +673,7 @@ int grape_launch(int mode, const tnrg_model* md, const double* ux, const double*
   {
     Fnv f;
     f.add(md->n), f.add(md->m), f.add(md->dt), f.add(md->chi), f.add(md->trunc_eps);
-    f.add(md->renormalize), f.add(d.max_sweeps), f.add(d.order);
+    f.add(md->renormalize), f.add(d.max_sweeps), f.add(d.order), f.add(d.heis);
     for (int b = 0; b + 1 < md->n; ++b) f.add(md->zz_mask[b]), f.add(md->xt_mask[b]);
     f.add(ux), f.add(uy), f.add(uzz), f.add(J), f.add(K), f.add(R), f.add(cap), f.add(cs);
     f.add(inputs->data), f.add(targets->data), f.add(ws);
@@ -657,14 +681,22 @@ int grape_launch(int mode, const tnrg_model* md, const double* ux, const double*
   }
 
   if (mode & kModeForward) launch_gates(md, ux, uy, gates, s);
-  const void* kern = in_lds ? reinterpret_cast<const void*>(lds::k_grape)
-                            : reinterpret_cast<const void*>(big::k_grape);
+  const bool mid = d.hgrad;
+  const void* kern = in_lds ? (mid ? reinterpret_cast<const void*>(lds::k_grape<true>)
+                                   : reinterpret_cast<const void*>(lds::k_grape<false>))
+                            : (mid ? reinterpret_cast<const void*>(big::k_grape<true>)
+                                   : reinterpret_cast<const void*>(big::k_grape<false>));
   hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute(k_grape)");
-  if (in_lds)
-    hipLaunchKernelGGL(lds::k_grape, dim3(K * R), dim3(threads_for_cap(cap)), lds, s, A);
+  const dim3 grid(K * R), block(threads_for_cap(cap));
+  if (in_lds && mid)
+    hipLaunchKernelGGL(lds::k_grape<true>, grid, block, lds, s, A);
+  else if (in_lds)
+    hipLaunchKernelGGL(lds::k_grape<false>, grid, block, lds, s, A);
+  else if (mid)
+    hipLaunchKernelGGL(big::k_grape<true>, grid, block, 0, s, A);
   else
-    hipLaunchKernelGGL(big::k_grape, dim3(K * R), dim3(threads_for_cap(cap)), 0, s, A);
+    hipLaunchKernelGGL(big::k_grape<false>, grid, block, 0, s, A);
   e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "k_grape launch");
   const int MN = md->m * md->n;

@@ -123,7 +123,7 @@ struct Slot {
   std::unique_ptr<Job> job;
 };
 
-using PlanKey = std::tuple<int, int, int, int, int>;  // N, M, chi, K, R
+using PlanKey = std::tuple<int, int, int, int, int, int>;  // N, M, chi, xt_model, K, R
 
 // The capacity-bucket plan: the last bucket that held every bond of a request
 // of this shape, shared by all servers of the process.
@@ -255,7 +255,7 @@ int reap(tnrg_server* s) {
       status = TNRG_ENONFINITE;
     if (status == TNRG_OK && job->req.dcap == 0) {
       const tnrg_model& m = job->model;
-      plan_put(PlanKey(m.n, m.m, m.chi, job->req.K, job->req.R), job->buckets[job->bucket]);
+      plan_put(PlanKey(m.n, m.m, m.chi, m.xt_model, job->req.K, job->req.R), job->buckets[job->bucket]);
     }
     complete(s, std::move(job), status);
   }
@@ -370,7 +370,7 @@ int tnrg_server_submit(tnrg_server* s, const tnrg_request* req, int64_t* ticket)
   if (req->dcap > 0) {
     job->buckets = {req->dcap};
   } else {
-    job->buckets = bucket_sequence(job->model, plan_get(PlanKey(md->n, md->m, md->chi, req->K, req->R)),
+    job->buckets = bucket_sequence(job->model, plan_get(PlanKey(md->n, md->m, md->chi, md->xt_model, req->K, req->R)),
                                    s->max_dcap);
   }
   job->ticket = s->next_ticket++;

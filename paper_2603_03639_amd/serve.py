@@ -43,6 +43,7 @@ class Request:
         self.g_ux = z(M, N) if self.g_ux is None else self.g_ux
         self.g_uy = z(M, N) if self.g_uy is None else self.g_uy
         self.g_uzz = z(M, N - 1) if self.g_uzz is None else self.g_uzz
+        self.model.check_J(self.J, int(self.J.shape[0]))
         if self.overlaps is None:
             self.overlaps = torch.zeros(int(self.J.shape[0]) * self.inputs.n_traj,
                                         dtype=torch.complex128, device=dev)

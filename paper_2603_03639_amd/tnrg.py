@@ -53,7 +53,8 @@ class _Model(ctypes.Structure):
                 ("profile", ctypes.c_int32),
                 ("zz_mask", ctypes.POINTER(ctypes.c_uint8)),
                 ("xt_mask", ctypes.POINTER(ctypes.c_uint8)),
-                ("split_order", ctypes.c_int32)]
+                ("split_order", ctypes.c_int32),
+                ("xt_model", ctypes.c_int32)]
 
 
 class _Batch(ctypes.Structure):
@@ -166,6 +167,13 @@ class Model:
     zz_mask: Optional[np.ndarray] = None
     xt_mask: Optional[np.ndarray] = None
     order: int = 2  # Trotter split: 2 (R Z R) or 1 (the first-order X Y Z)
+    xt_model: int = 0  # crosstalk: 0 = J ZZ, 1 = J^x XX + J^y YY + J^z ZZ (Sec. III Eq. 9)
+
+    def check_J(self, J, rows: int) -> None:
+        """J must be [rows][N-1] (xt_model 0) or [rows][N-1][3] (xt_model 1)."""
+        want = (rows, self.N - 1) + ((3,) if self.xt_model == 1 else ())
+        if tuple(J.shape) != want:
+            raise ValueError(f"J has shape {tuple(J.shape)}, the model needs {want}")
 
     def c(self) -> _Model:
         zz = np.ascontiguousarray(self.zz_mask if self.zz_mask is not None
@@ -176,7 +184,8 @@ class Model:
                    1 if self.renormalize else 0, int(self.max_sweeps),
                    1 if self.profile else 0,
                    zz.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
-                   xt.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), int(self.order))
+                   xt.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), int(self.order),
+                   int(self.xt_model))
         m._keep = (zz, xt)
         return m
 
@@ -184,7 +193,8 @@ class Model:
     def from_problem(cls, p, **kw) -> "Model":
         return cls(N=p.N, M=p.M, dt=p.dt, chi=p.chi, eps=p.eps,
                    renormalize=p.renormalize, zz_mask=p.zz_mask,
-                   xt_mask=p.xt_mask, order=getattr(p, "order", 2), **kw)
+                   xt_mask=p.xt_mask, order=getattr(p, "order", 2),
+                   xt_model=1 if getattr(p, "xt_model", "zz") == "heisenberg" else 0, **kw)
 
 
 def bond_cap(N: int, dcap: int, b: int) -> int:
@@ -296,10 +306,12 @@ def _f64(x, device):
 # ----------------------------------------------------------------------------
 def mps_evolve(model: Model, ux, uy, uzz, J, psi: MPSBatch, l_begin=0, l_end=None,
                adjoint=False, stream=None, check=True):
-    """In-place evolution of a batch (J: [n_traj][N-1])."""
+    """In-place evolution of a batch (J: [n_traj][N-1], or [n_traj][N-1][3]
+    with Heisenberg crosstalk)."""
     dev = psi.data.device
     l_end = model.M if l_end is None else l_end
     ux, uy, uzz, J = (_f64(a, dev) for a in (ux, uy, uzz, J))
+    model.check_J(J, psi.n_traj)
     cm = model.c()
     nbytes = _lib.mps_evolve_workspace_bytes(ctypes.byref(cm), psi.n_traj, psi.dcap)
     ws = _workspace(nbytes, dev)
@@ -409,7 +421,8 @@ def prepare(model: Model, ux, uy, uzz, J, inputs: MPSBatch, targets: MPSBatch,
     dev = inputs.data.device
     K = int(J.shape[0])
     R = inputs.n_traj
-    key = (model.N, model.M, model.chi, K, R)
+    model.check_J(J, K)
+    key = (model.N, model.M, model.chi, model.xt_model, K, R)
     start = dcap if dcap is not None else _plan_cache.get(key)
     seq = [dcap] if dcap is not None else _bucket_sequence(model, start)
     last = None
@@ -445,7 +458,8 @@ def grape_fidelity_grad(model: Model, ux, uy, uzz, J, inputs: MPSBatch, targets:
     K = int(J.shape[0])
     R = inputs.n_traj
     ux, uy, uzz, J = (_f64(a, dev) for a in (ux, uy, uzz, J))
-    key = (model.N, model.M, model.chi, K, R)
+    model.check_J(J, K)
+    key = (model.N, model.M, model.chi, model.xt_model, K, R)
     start = dcap if dcap is not None else _plan_cache.get(key)
     seq = [dcap] if dcap is not None else _bucket_sequence(model, start)
     last = None
