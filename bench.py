@@ -40,7 +40,7 @@ import os, sys, time, json
 sys.path.insert(0, {root!r})
 import workloads as W
 from oracle import grape
-p = W.make_problem({name!r})
+p = W.make_problem({name!r}, xt_model={xt!r})
 t0 = time.perf_counter()
 for r in range({n}):
     grape.trajectory(p, 0, r)
@@ -49,9 +49,13 @@ print(json.dumps(dict(seconds=dt)))
 """
 
 
-def cpu_baseline(name, n_traj, R):
+TASKS = {"x": "parallel X gate", "cnot": "parallel CNOT", "ghz": "GHZ state preparation",
+         "heisenberg": "Heisenberg ground-state preparation"}
+
+
+def cpu_baseline(name, n_traj, R, xt_model="zz"):
     env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
-    code = CPU_SCRIPT.format(root=ROOT, name=name, n=n_traj)
+    code = CPU_SCRIPT.format(root=ROOT, name=name, n=n_traj, xt=xt_model)
     out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True,
                          timeout=900)
     if out.returncode != 0:
@@ -61,7 +65,7 @@ def cpu_baseline(name, n_traj, R):
     samples = n_traj / R
     return {"value": samples / secs, "unit": "noise-samples/s", "cores": 1, "kind": "oracle",
             "sample": f"{n_traj} of the {R} trajectories of noise sample k=0 (forward + adjoint "
-                      f"over all 200 slices), one process, 1 BLAS thread: {secs:.2f} s",
+                      f"over all slices), one process, 1 BLAS thread: {secs:.2f} s",
             "seconds": secs}
 
 
@@ -247,6 +251,9 @@ def main():
     ap.add_argument("--ckpt-stride", type=int, default=None,
                     help="checkpoint stride of the adjoint sweep (0: ceil(sqrt(M)); "
                          "default: the smallest that fits 60%% of the free HBM)")
+    ap.add_argument("--xt-model", choices=("zz", "heisenberg"), default="zz",
+                    help="crosstalk: the workload's J ZZ (default), or the paper's "
+                         "J^x XX + J^y YY + J^z ZZ, uniform in [-0.05, 0.05], on every bond")
     ap.add_argument("--plain", type=int, default=8,
                     help="trajectories run one at a time for the plain GPU path (0 disables)")
     args = ap.parse_args()
@@ -267,8 +274,10 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
-    p = W.make_problem(args.workload)
-    log(f"workload {args.workload}: N={p.N} M={p.M} chi={p.chi} K={p.K} R={p.R}")
+    p = W.make_problem(args.workload, xt_model=args.xt_model)
+    heis = args.xt_model == "heisenberg"
+    wname = args.workload + ("_heisenberg" if heis else "")
+    log(f"workload {wname}: N={p.N} M={p.M} chi={p.chi} K={p.K} R={p.R}")
     f = lambda a: torch.as_tensor(np.ascontiguousarray(a, np.float64), device=dev)
     ux, uy, uzz, J = f(p.ux), f(p.uy), f(p.uzz), f(p.J)
     inputs = P.MPSBatch.from_product(p.inputs, device=dev)
@@ -330,7 +339,7 @@ def main():
     achieved = flops / (kern_ms / 1000.0) / 1e12
     roofline = {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
-                "traffic": stored_traffic(args.workload, ck["stride"]),
+                "traffic": stored_traffic(wname, ck["stride"]),
                 "kernel": "k_grape", "flops_per_launch": flops,
                 "jacobi_flops_per_launch": info["jacobi_flops"],
                 "contraction_flops_per_launch": info["contraction_flops"],
@@ -407,14 +416,17 @@ def main():
     cpu = None
     if args.cpu_sample > 0:
         log("timing the CPU oracle ...")
-        cpu = cpu_baseline(args.workload, min(args.cpu_sample, p.R), p.R)
+        cpu = cpu_baseline(args.workload, min(args.cpu_sample, p.R), p.R, args.xt_model)
 
     out = {
         "metric": METRIC, "value": value, "unit": "noise-samples/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": f"{args.workload}: parallel CNOT, N={p.N}, chi={p.chi}, M={p.M}, "
-                               f"K={p.K} noise samples x R={p.R} inputs, T={p.T}",
+        "config": {"workload": f"{wname}: {TASKS.get(p.task, p.task)}, N={p.N}, chi={p.chi}, "
+                               f"M={p.M}, K={p.K} noise samples x R={p.R} inputs, T={p.T:.4g}, "
+                               + ("Heisenberg crosstalk J^x XX + J^y YY + J^z ZZ, uniform in "
+                                  "[-0.05, 0.05], every bond" if heis else
+                                  "ZZ crosstalk Normal(0, sigma)"),
                    "N": p.N, "chi": p.chi, "M": p.M, "K": p.K, "R": p.R,
                    "dcap": plan["dcap"], "max_bond_dim": info["max_dim"],
                    "ckpt_stride": ck["stride"], "workspace_gib": ck["workspace_bytes"] / 2**30,
