@@ -254,6 +254,8 @@ def main():
     ap.add_argument("--xt-model", choices=("zz", "heisenberg"), default="zz",
                     help="crosstalk: the workload's J ZZ (default), or the paper's "
                          "J^x XX + J^y YY + J^z ZZ, uniform in [-0.05, 0.05], on every bond")
+    ap.add_argument("--K", type=int, default=0,
+                    help="noise samples: the first K of the workload's (0: all of them)")
     ap.add_argument("--plain", type=int, default=8,
                     help="trajectories run one at a time for the plain GPU path (0 disables)")
     args = ap.parse_args()
@@ -277,6 +279,10 @@ def main():
     p = W.make_problem(args.workload, xt_model=args.xt_model)
     heis = args.xt_model == "heisenberg"
     wname = args.workload + ("_heisenberg" if heis else "")
+    if args.K and args.K < p.K:
+        p = p.subset(ks=range(args.K))
+        wname += f"_K{args.K}"
+
     log(f"workload {wname}: N={p.N} M={p.M} chi={p.chi} K={p.K} R={p.R}")
     f = lambda a: torch.as_tensor(np.ascontiguousarray(a, np.float64), device=dev)
     ux, uy, uzz, J = f(p.ux), f(p.uy), f(p.uzz), f(p.J)

@@ -163,7 +163,7 @@ int mps_overlap(const tnrg_mps_batch *bra, const tnrg_mps_batch *ket,
  * inside the sweep, between the forward state just after bond b and the
  * backward state just before it (App. A for the ordered bond product); the
  * adjoint then also re-runs each forward slice once to recover the forward
- * states inside it, and the workspace holds ckpt_stride more MPS.
+ * states inside it, and the workspace holds one more MPS.
  *   J: device [K][N-1] (xt_model 0) or [K][N-1][3] (xt_model 1).
  *   inputs: R MPS (each canonical with centre on site 0; product states are).
  *   targets: R MPS, right-canonical with unit norm (sites 1..N-1

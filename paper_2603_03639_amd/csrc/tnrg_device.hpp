@@ -840,8 +840,12 @@ struct GradOut {
 //     of <b_{l+1}|a_{l+1}> (site-local factors cancel in it); the one on the
 //     side it has passed is grown bond by bond from the final backward sites
 //     and the input sites of a_l (the pre factor cancels there).
-constexpr int kSweepPlain = 0, kSweepCentres = 1, kSweepInsert = 2;
+// kSweepPlain and kSweepMid are the template argument of slice_sweep; a
+// kSweepMid sweep does the work of ex->mode (kSweepCentres or kSweepInsert),
+// so that both passes share one instance of the sweep.
+constexpr int kSweepPlain = 0, kSweepMid = 3, kSweepCentres = 1, kSweepInsert = 2;
 struct SweepExtra {
+  int mode;          // kSweepCentres or kSweepInsert
   c2* cen;           // centres of the forward re-run
   const c2* a_next;  // a_{l+1} and its dims
   const int* dn;
@@ -988,7 +992,7 @@ __device__ __forceinline__ void save_centre(Ctx& C, c2* site, int dl, int dr, in
 // Eq. 4, second order).  Z applies the bond gates in sweep order.  For an
 // adjoint slice G = R^dag and every bond gate is replaced by its adjoint
 // (time t -> -t).  src may equal dst.  kX and ex: the extra work described
-// at SweepExtra (dst and dst_dims may be null with kSweepCentres).
+// at SweepExtra (dst and dst_dims may be null for the kSweepCentres pass).
 template <int kX>
 __device__ __forceinline__ void slice_sweep(Ctx& C, const c2* src, const int* src_dims, c2* dst,
                             int* dst_dims, bool ltr, const c2* gates, int l, bool dag,
@@ -1035,10 +1039,12 @@ __device__ __forceinline__ void slice_sweep(Ctx& C, const c2* src, const int* sr
       if (ex->go->dO) ex->go->dO[idx] = cadd(ex->go->dO[idx], v);
     }
   };
+  const bool cen_mode = kX == kSweepMid && ex->mode == kSweepCentres;
+  const bool ins_mode = kX == kSweepMid && ex->mode == kSweepInsert;
   int cur = 0;  // ping-pong half of ex->inc holding the grown environment
   if (ltr) {
     load_site(C, C.LC, src + L.off[0], 1, C.sdims[1], L.cap[1], gload(0));
-    if (kX == kSweepInsert && C.tid == 0) ex->inc[0] = cmk(1.0, 0.0);
+    if (ins_mode && C.tid == 0) ex->inc[0] = cmk(1.0, 0.0);
     __syncthreads();
     for (int b = 0; b < N - 1; ++b) {
       const int dl = C.sdims[b], dm = C.sdims[b + 1], dr = C.sdims[b + 2];
@@ -1046,7 +1052,7 @@ __device__ __forceinline__ void slice_sweep(Ctx& C, const c2* src, const int* sr
       load_site(C, C.LO, src + L.off[b + 1], dm, dr, L.cap[b + 2], gload(b + 1));
       __syncthreads();
       ph_add(C, kPhLoad, tl);
-      if (kX == kSweepInsert && bit(C.md.zzm, b)) {
+      if (ins_mode && bit(C.md.zzm, b)) {
         const int* dp = ex->dp;
         const int* dn = ex->dn;
         const c2 v = zz_sandwich(C, ex->inc + cur * cc, dp[b], 1, C.LC, dm, ex->cen + L.off[b],
@@ -1059,8 +1065,8 @@ __device__ __forceinline__ void slice_sweep(Ctx& C, const c2* src, const int* sr
                                dst ? dst + L.off[b] : nullptr, L.cap[b + 1], gfin(b), L.cap[b + 1]);
       if (C.tid == 0) C.sdims[b + 1] = k;
       __syncthreads();
-      if (kX == kSweepCentres) save_centre(C, ex->cen + L.off[b + 1], k, dr, L.cap[b + 2]);
-      if (kX == kSweepInsert && b < C.md.zz_hi) {
+      if (cen_mode) save_centre(C, ex->cen + L.off[b + 1], k, dr, L.cap[b + 2]);
+      if (ins_mode && b < C.md.zz_hi) {
         const int* dp = ex->dp;
         grow_left(C, dst + L.off[b], L.cap[b + 1], ex->a_prev + L.off[b], L.cap[b + 1],
                   ex->inc + cur * cc, ex->inc + (1 - cur) * cc, k, dl, dp[b + 1], dp[b]);
@@ -1070,7 +1076,7 @@ __device__ __forceinline__ void slice_sweep(Ctx& C, const c2* src, const int* sr
     if (dst) store_site(C, dst + L.off[N - 1], C.LC, C.sdims[N - 1], 1, L.cap[N], gfin(N - 1));
   } else {
     load_site(C, C.LC, src + L.off[N - 1], C.sdims[N - 1], 1, L.cap[N], gload(N - 1));
-    if (kX == kSweepInsert && C.tid == 0) ex->inc[0] = cmk(1.0, 0.0);
+    if (ins_mode && C.tid == 0) ex->inc[0] = cmk(1.0, 0.0);
     __syncthreads();
     for (int b = N - 2; b >= 0; --b) {
       const int dl = C.sdims[b], dm = C.sdims[b + 1], dr = C.sdims[b + 2];
@@ -1078,7 +1084,7 @@ __device__ __forceinline__ void slice_sweep(Ctx& C, const c2* src, const int* sr
       load_site(C, C.LO, src + L.off[b], dl, dm, L.cap[b + 1], gload(b));
       __syncthreads();
       ph_add(C, kPhLoad, tl);
-      if (kX == kSweepInsert && bit(C.md.zzm, b)) {
+      if (ins_mode && bit(C.md.zzm, b)) {
         const int* dp = ex->dp;
         const int* dn = ex->dn;
         const c2 v = zz_sandwich(C, ex->envs + (size_t)b * cc, dn[b], 1, C.LO, dm,
@@ -1092,8 +1098,8 @@ __device__ __forceinline__ void slice_sweep(Ctx& C, const c2* src, const int* sr
                                L.cap[b + 1]);
       if (C.tid == 0) C.sdims[b + 1] = k;
       __syncthreads();
-      if (kX == kSweepCentres) save_centre(C, ex->cen + L.off[b], dl, k, L.cap[b + 1]);
-      if (kX == kSweepInsert && b > C.md.zz_lo) {
+      if (cen_mode) save_centre(C, ex->cen + L.off[b], dl, k, L.cap[b + 1]);
+      if (ins_mode && b > C.md.zz_lo) {
         const int* dp = ex->dp;
         grow_right(C, dst + L.off[b + 1], L.cap[b + 2], ex->a_prev + L.off[b + 1], L.cap[b + 2],
                    ex->inc + cur * cc, ex->inc + (1 - cur) * cc, k, dr, dp[b + 1], dp[b + 2]);
@@ -1118,26 +1124,28 @@ __device__ __forceinline__ void forward_slice(Ctx& C, const c2* src, const int* 
   slice_sweep<kSweepPlain>(C, src, sd, dst, dd, forward_ltr(C, l), gates, l, false, 1.0, uzz, Jrow,
                            nullptr);
 }
-// Forward re-run of slice l keeping the centres (kSweepCentres); dst, dd
-// may be null.
-__device__ __forceinline__ void forward_centres(Ctx& C, const c2* src, const int* sd, c2* dst,
-                                                int* dd, const c2* gates, int l, const double* uzz,
-                                                const double* Jrow, const SweepExtra* ex) {
-  slice_sweep<kSweepCentres>(C, src, sd, dst, dd, forward_ltr(C, l), gates, l, false, 1.0, uzz,
-                             Jrow, ex);
-}
 // Adjoint slice l (0-based): b_l = U_l^dag b_{l+1}; left to right when
-// M - 1 - l is even.  With ex, the mid-sweep u^zz insertions (kSweepInsert).
+// M - 1 - l is even.
 __device__ __forceinline__ void adjoint_slice(Ctx& C, const c2* src, const int* sd, c2* dst,
                                               int* dd, const c2* gates, int l,
-                                              const double* uzz, const double* Jrow,
-                                              const SweepExtra* ex = nullptr) {
-  if (ex)
-    slice_sweep<kSweepInsert>(C, src, sd, dst, dd, !forward_ltr(C, l), gates, l, true, -1.0, uzz,
-                              Jrow, ex);
-  else
-    slice_sweep<kSweepPlain>(C, src, sd, dst, dd, !forward_ltr(C, l), gates, l, true, -1.0, uzz,
-                             Jrow, nullptr);
+                                              const double* uzz, const double* Jrow) {
+  slice_sweep<kSweepPlain>(C, src, sd, dst, dd, !forward_ltr(C, l), gates, l, true, -1.0, uzz,
+                           Jrow, nullptr);
+}
+// Adjoint slice l with the mid-sweep u^zz insertions: forward slice l re-run
+// from a_l (ex.a_prev) keeping its centres, then the backward slice of b (in
+// place) with the insertions; one instance of the sweep serves both passes.
+__device__ __forceinline__ void adjoint_slice_mid(Ctx& C, c2* b, int* bd, const c2* gates, int l,
+                                                  const double* uzz, const double* Jrow,
+                                                  SweepExtra& ex) {
+  const bool fl = forward_ltr(C, l);
+  for (int pass = 0; pass < 2; ++pass) {
+    const bool ins = pass == 1;
+    ex.mode = ins ? kSweepInsert : kSweepCentres;
+    slice_sweep<kSweepMid>(C, ins ? b : ex.a_prev, ins ? bd : ex.dp, ins ? b : nullptr,
+                           ins ? bd : nullptr, ins ? !fl : fl, gates, l, ins, ins ? -1.0 : 1.0,
+                           uzz, Jrow, &ex);
+  }
 }
 
 // Copy one MPS between two capacity layouts (dims must fit the destination).

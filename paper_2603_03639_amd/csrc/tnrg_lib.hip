@@ -370,8 +370,8 @@ struct GrapeLayout {
 };
 
 // Heisenberg crosstalk with some u^zz control: the adjoint takes the u^zz
-// derivative inside its sweeps (more workspace: the centres of one segment
-// and two environment buffers).
+// derivative inside its sweeps (more workspace: one MPS slot for the
+// centres of a forward slice and two environment buffers).
 bool mid_sweep_zz(const tnrg_model* md) {
   if (md->xt_model != 1) return false;
   for (int b = 0; b < md->n - 1; ++b)
@@ -386,7 +386,7 @@ GrapeLayout grape_layout(const tnrg_model* md, int K, int R, int dcap, int cs) {
   g.cs = cs;
   g.nck = (M + cs - 1) / cs;
   const bool hg = mid_sweep_zz(md);
-  g.nslots = g.nck + cs + 2 + (hg ? cs : 0);
+  g.nslots = g.nck + cs + 2 + (hg ? 1 : 0);
   g.nctrl = 2 * M * N + M * (N - 1);
   const size_t elems = (size_t)site_offset_slow(N, dcap, N);
   g.dims_off = align256(elems * sizeof(c2));

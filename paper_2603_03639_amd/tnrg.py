@@ -432,6 +432,10 @@ def prepare(model: Model, ux, uy, uzz, J, inputs: MPSBatch, targets: MPSBatch,
         info = call.check(stream, raise_on_error=False)
         if info["rc"] == EOVERFLOW and dcap is None:
             last = info
+            # hand the overflowed bucket's workspace back before the next,
+            # larger one is allocated
+            call = None
+            torch.cuda.empty_cache()
             continue
         if info["rc"] != OK:
             raise TnrgError(info["rc"], _lib.tnrg_last_error().decode())
@@ -469,6 +473,10 @@ def grape_fidelity_grad(model: Model, ux, uy, uzz, J, inputs: MPSBatch, targets:
         info = call.check(stream, raise_on_error=False)
         if info["rc"] == EOVERFLOW and dcap is None:
             last = info
+            # hand the overflowed bucket's workspace back before the next,
+            # larger one is allocated
+            call = None
+            torch.cuda.empty_cache()
             continue
         if info["rc"] != OK:
             raise TnrgError(info["rc"], _lib.tnrg_last_error().decode())

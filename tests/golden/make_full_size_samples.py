@@ -8,10 +8,11 @@ the overlap O_kr = <T_r|a_M> and dO_kr/du at a seeded sample of control
 indices (flat order ux [M][N], uy [M][N], uzz [M][N-1]), plus the index and
 value of the largest |dO| entry and the bond dimensions the trajectory
 reached.  A name ending in "_self" is the self-target variant of the
-workload (tests/golden/self_target.py).  Only `workloads` (seeded inputs) and
+workload (tests/golden/self_target.py); "_heisenberg" after the workload
+name selects the paper's Heisenberg-type crosstalk.  Only `workloads` (seeded inputs) and
 `oracle/` are used.
 
-    python tests/golden/make_full_size_samples.py [workload ...]
+    [GOLDEN_WORKERS=n] python tests/golden/make_full_size_samples.py [workload ...]
 """
 import json
 import os
@@ -27,7 +28,7 @@ import workloads as W  # noqa: E402
 from oracle import grape  # noqa: E402
 
 sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
-from self_target import self_target  # noqa: E402
+from self_target import golden_problem  # noqa: E402
 
 OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "full_size_samples.json")
 
@@ -45,20 +46,30 @@ def pick(p, rng):
     return sorted(ts)
 
 
-def sample(name):
-    base = name[:-5] if name.endswith("_self") else name
-    p = W.make_problem(base)
-    if name != base:
-        p = self_target(p)
+def _one(args):
+    name, k, r = args
+    p, _ = golden_problem(name)
+    t0 = time.perf_counter()
+    st = []
+    O, dux, duy, duzz = grape.trajectory(p, k, r, stats=st)
+    flat = np.concatenate([dux.ravel(), duy.ravel(), duzz.ravel()])
+    return O, flat, int(max(s["k"] for s in st)), time.perf_counter() - t0
+
+
+def sample(name, workers=1):
+    p, base = golden_problem(name)
     rng = np.random.default_rng([SEED, sum(map(ord, name))])
     nctrl = 2 * p.M * p.N + p.M * (p.N - 1)
+    ts = pick(p, rng)
+    jobs = [(name,) + divmod(t, p.R) for t in ts]
+    if workers > 1:
+        from concurrent.futures import ProcessPoolExecutor
+        with ProcessPoolExecutor(workers) as ex:
+            results = list(ex.map(_one, jobs))
+    else:
+        results = [_one(j) for j in jobs]
     out = []
-    for t in pick(p, rng):
-        k, r = divmod(t, p.R)
-        t0 = time.perf_counter()
-        st = []
-        O, dux, duy, duzz = grape.trajectory(p, k, r, stats=st)
-        flat = np.concatenate([dux.ravel(), duy.ravel(), duzz.ravel()])
+    for (_, k, r), (O, flat, dmax, secs) in zip(jobs, results):
         assert flat.size == nctrl
         idx = np.sort(rng.choice(nctrl, size=N_ENTRIES, replace=False))
         imax = int(np.argmax(np.abs(flat)))
@@ -70,11 +81,11 @@ def sample(name):
             "dO_argmax": imax,
             "dO_max": [flat[imax].real, flat[imax].imag],
             "dO_inf": float(np.max(np.abs(flat))),
-            "max_bond_dim": int(max(s["k"] for s in st)),
+            "max_bond_dim": dmax,
         })
         print(f"{name} (k={k}, r={r}): |O|={abs(O):.3e} |dO|_inf={out[-1]['dO_inf']:.3e} "
-              f"max D={out[-1]['max_bond_dim']} {time.perf_counter() - t0:.1f} s", flush=True)
-    cfg = dict(W.CONFIGS[base], self_target=name != base)
+              f"max D={dmax} {secs:.1f} s", flush=True)
+    cfg = dict(W.CONFIGS[base], self_target=name.endswith("_self"), xt_model=p.xt_model)
     return {"config": cfg, "nctrl": nctrl, "trajectories": out}
 
 
@@ -86,8 +97,9 @@ def main():
             data = json.load(f)
     data["_about"] = ("Oracle values (tests/golden/make_full_size_samples.py) for sampled "
                       "trajectories of the full-size workloads; controls index order ux, uy, uzz.")
+    workers = int(os.environ.get("GOLDEN_WORKERS", "1"))
     for name in names:
-        data[name] = sample(name)
+        data[name] = sample(name, workers)
     with open(OUT, "w") as f:
         json.dump(data, f, indent=1)
 

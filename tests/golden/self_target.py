@@ -15,9 +15,22 @@ from oracle import mps as omps, tebd as otebd
 
 
 def self_target(p):
-    quiet = dataclasses.replace(p, J=np.zeros((1, p.N - 1)))
+    quiet = dataclasses.replace(p, J=np.zeros((1,) + p.J.shape[1:]))
     targets = []
     for r in range(p.R):
         a = otebd.evolve(quiet, omps.product_state(p.inputs[r]), 0)
         targets.append(omps.right_canonicalize(a))
     return dataclasses.replace(p, targets=targets, name=p.name + "_self")
+
+
+def golden_problem(name):
+    """The problem a full-size sample name stands for: a workload name, then
+    optionally "_heisenberg" (the paper's XX + YY + ZZ crosstalk instead of
+    the workload's ZZ one) and "_self" (the self-target variant)."""
+    import workloads as W
+    self_t = name.endswith("_self")
+    n = name[:-len("_self")] if self_t else name
+    heis = n.endswith("_heisenberg")
+    base = n[:-len("_heisenberg")] if heis else n
+    p = W.make_problem(base, xt_model="heisenberg" if heis else "zz")
+    return (self_target(p) if self_t else p), base
