@@ -49,3 +49,66 @@ def test_lbfgs_raises_the_ensemble_fidelity(P):
         g = chk[nm].cpu().numpy()
         scale = max(np.max(np.abs(ref[nm])), 1e-300)
         assert np.max(np.abs(g - ref[nm])) <= 1e-10 * scale + 1e-15, nm
+
+
+def _dev(P, p):
+    d = device_problem(p)
+    return dict(model=d["model"], J=d["J"], inputs=d["inputs"], targets=d["targets"],
+                ux=d["ux"], uy=d["uy"], uzz=d["uzz"])
+
+
+def test_warm_start_in_system_size(P):
+    """The n = 4 solution, extended, seeds n = 6 (Sec. II): it starts far
+    above a random start and the optimisation keeps improving it."""
+    mk = lambda n: W.make_problem(task="x", N=n, M=12, T=4.0, chi=8, K=2, R=2, sigma=0.02, seed=5)
+    print("sequential: x gate N = 4 -> 6", flush=True)
+    p4 = mk(4)
+    out = P.optimize.sequential([4, 6], lambda n: _dev(P, mk(n)), p4.ux, p4.uy, p4.uzz, iters=15)
+    F_rand6 = og.fidelity_grad(mk(6))["F"]
+    print(f"  N=4: {out[0]['F_start']:.4f} -> {out[0]['F']:.4f}; N=6: random {F_rand6:.4f}, "
+          f"warm {out[1]['F_start']:.4f} -> {out[1]['F']:.4f}", flush=True)
+    assert out[0]["F"] > 0.9
+    assert out[1]["F_start"] > 0.8 and out[1]["F_start"] > 10 * F_rand6
+    assert out[1]["F"] >= out[1]["F_start"]
+    for st in out:
+        assert all(b >= a - 1e-12 for a, b in zip(st["history"], st["history"][1:]))
+
+
+def test_robustness_continuation(P):
+    """Error strength raised in 1 % steps with Heisenberg crosstalk, each
+    stage seeded by the previous one (Sec. II)."""
+    mk = lambda dj: W.make_problem(task="cnot", N=4, M=12, T=6.0, chi=8, K=3, R=2, seed=9,
+                                   xt_model="heisenberg", delta_j=dj)
+    steps = P.optimize.robustness_steps(0.02)
+    print(f"sequential: cnot N=4, dJ steps {steps}", flush=True)
+    p0 = mk(0.0)
+    out = P.optimize.sequential(steps, lambda dj: _dev(P, mk(dj)), p0.ux, p0.uy, p0.uzz, iters=12)
+    for st in out:
+        print(f"  dJ={st['stage']:.2f}: {st['F_start']:.4f} -> {st['F']:.4f}", flush=True)
+        assert all(b >= a - 1e-12 for a, b in zip(st["history"], st["history"][1:]))
+    assert [st["stage"] for st in out] == steps
+    assert out[-1]["F"] > out[0]["F_start"]
+    # each later stage starts from the previous solution
+    for a, b in zip(out, out[1:]):
+        assert b["F_start"] > 0.5 * a["F"]
+
+
+def test_two_stage_ensemble(P):
+    """Optimise on K = 2 n_J noise samples, estimate on 5 K fresh ones; the
+    estimate is the oracle's fidelity of that ensemble at the optimised
+    controls."""
+    mk = lambda K, stage: W.make_problem(task="x", N=4, M=10, T=4.0, chi=8, K=K, R=2, sigma=0.05,
+                                         seed=100 + stage)
+    p = mk(1, 0)
+    n_j = P.optimize.parasitic_count(P.Model.from_problem(p))
+    assert n_j == 3
+    print("two-stage ensemble: x gate N=4", flush=True)
+    res = P.optimize.two_stage(lambda K, st: _dev(P, mk(K, st)), p.ux, p.uy, p.uzz, n_j, iters=20)
+    assert (res["K_train"], res["K_eval"]) == (6, 30)
+    e = dataclasses.replace(mk(30, 1), ux=res["ux"].cpu().numpy(), uy=res["uy"].cpu().numpy(),
+                            uzz=res["uzz"].cpu().numpy())
+    ref = og.fidelity_grad(e)["F"]
+    print(f"  F_train {res['F_train']:.5f}, F_eval {res['F_eval']:.5f} (oracle {ref:.5f})",
+          flush=True)
+    assert res["F_train"] > 0.9
+    assert abs(res["F_eval"] - ref) <= 1e-10 * ref
