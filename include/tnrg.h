@@ -254,6 +254,17 @@ int tnrg_plan_set_threads(int32_t dcap, int32_t threads);
 int32_t tnrg_plan_threads(int32_t dcap);
 
 /*
+ * Launch plan (process-wide) for capacities above 32: the one-sided Jacobi
+ * SVD of a bond update (Sec. II, the truncated SVD) runs on a copy of its
+ * matrix in LDS when it fits (about 150 KB: at most 72 columns of 128 rows),
+ * which then leaves room for one workgroup per CU.  mode -1 (default) or 1:
+ * on; 0: off (the matrix stays in the workspace and several workgroups
+ * share a CU).  Results are bitwise the same either way.  TNRG_EINVAL for
+ * other modes.
+ */
+int tnrg_plan_set_jacobi_lds(int32_t mode);
+
+/*
  * Serving runtime: a request loop that runs fidelity+gradient evaluations of
  * concurrent optimisations (different N, chi, M, K, R) on one GPU with
  * continuous batching.  Each request is one persistent grape_fidelity_grad

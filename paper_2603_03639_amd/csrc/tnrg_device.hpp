@@ -89,6 +89,10 @@ struct Ctx {
   sdbl* sinv;        // LDS scalar: 1 / norm of kept singular values
   sdbl* sd;          // LDS scratch scalars [4]
   sint* si;          // LDS scratch scalars [4]
+  // global-scratch build: dynamic LDS that holds the Jacobi matrix of a bond
+  // update when it fits (jx_elems complex, 0 when there is none)
+  __attribute__((address_space(3))) c2* jx;
+  int jx_elems;
 };
 
 __device__ __forceinline__ void flag_or(Ctx& C, int v) {
@@ -373,9 +377,9 @@ __device__ __forceinline__ int lq_pivot(Ctx& C, sc2* Z, int nz, int mz, int ldz,
 // sweep they are dropped and the live columns are packed to the front, in
 // order.  Returns the number of live columns (>= 1); sig[c] holds ||X_c|| for
 // those.  *sweeps_out receives the number of sweeps.
-template <int RPL>
-__device__ __forceinline__ int jacobi_sweep(Ctx& C, sc2* X, int ldx, int n, int G, double thr2,
-                                            double tol2, sc2* dummy) {
+template <int RPL, class T>
+__device__ __forceinline__ int jacobi_sweep(Ctx& C, T* X, int ldx, int n, int G, double thr2,
+                                            double tol2, T* dummy) {
   const int tid = C.tid;
   const int P = (n + 1) >> 1;
   const int m = 2 * P - 1;
@@ -386,8 +390,8 @@ __device__ __forceinline__ int jacobi_sweep(Ctx& C, sc2* X, int ldx, int n, int 
   // one pair (ia, ib) of one round; idle slots work on two scratch columns
   // nobody reads, so the round is straight-line code without lane masking
   auto pair = [&](int ia, int ib, bool valid) {
-    sc2* xc = (valid ? X + ia * ldx : dummy) + r0;
-    sc2* yc = (valid ? X + ib * ldx : dummy + G * RPL) + r0;
+    T* xc = (valid ? X + ia * ldx : dummy) + r0;
+    T* yc = (valid ? X + ib * ldx : dummy + G * RPL) + r0;
     c2 x[RPL], y[RPL];
 #pragma unroll
     for (int i = 0; i < RPL; ++i) {
@@ -476,15 +480,15 @@ __device__ __forceinline__ int jacobi_sweep(Ctx& C, sc2* X, int ldx, int n, int 
   return rotated;
 }
 
-__device__ __forceinline__ int jacobi_lds(Ctx& C, sc2* X, int len, int ncol, int ldx, double thr2,
-                                          int* sweeps_out) {
+// X and dummy (two scratch columns of pad rows for idle pair slots) are in
+// LDS or in global scratch (T is the element type with its address space).
+template <class T>
+__device__ __forceinline__ int jacobi_lds(Ctx& C, T* X, int len, int ncol, int ldx, double thr2,
+                                          int* sweeps_out, T* dummy) {
   const int tid = C.tid, NT = C.nt;
   const double tol = (double)len * 2.220446049250313e-16;
   const double tol2 = tol * tol;
   const int pad = pow2_at_least(len);
-  // idle pair slots read and write two scratch columns of pad rows in the
-  // (free) LO buffer, which holds P2^2 / 2 >= 2 pad elements
-  sc2* dummy = C.LO;
   int n = ncol;
   int sweeps = 0;
   const int max_sweeps = C.md.max_sweeps;
@@ -494,7 +498,7 @@ __device__ __forceinline__ int jacobi_lds(Ctx& C, sc2* X, int len, int ncol, int
     const int Rc = pad / Gc;
     const int gc = tid / Gc, qc = tid % Gc;
     for (int c = gc; c < nn; c += NT / Gc) {
-      const sc2* xc = X + c * ldx + qc * Rc;
+      const T* xc = X + c * ldx + qc * Rc;
       double s = 0.0;
       for (int i = 0; i < Rc; ++i) s += cabs2(xc[i]);
       double red[1] = {s};
@@ -738,7 +742,22 @@ __device__ __forceinline__ int bond_split(Ctx& C, const sc2* Lt, const sc2* Rt, 
   const int rank = lq_pivot(C, Z, nc, len, ldz, X, ldx, &thr2);
   ph_add(C, kPhLQ, t0);
   int sw = 0;
-  const int nlive = jacobi_lds(C, X, len, rank, ldx, thr2, &sw);
+  int nlive;
+  const int padl = pow2_at_least(len);
+  if (TNRG_BIG && (long long)rank * ldx + 2 * padl <= C.jx_elems) {
+    // global-scratch build: the Jacobi runs on an LDS copy of L (the idle
+    // pair slots' scratch columns after it), which goes back for the finish
+    auto* J = C.jx;
+    for (int i = C.tid; i < rank * ldx; i += C.nt) J[i] = X[i];
+    __syncthreads();
+    nlive = jacobi_lds(C, J, len, rank, ldx, thr2, &sw, J + rank * ldx);
+    for (int i = C.tid; i < nlive * ldx; i += C.nt) X[i] = J[i];
+    __syncthreads();
+  } else {
+    // idle pair slots use two scratch columns of pad rows in the (free) LO
+    // buffer, which holds P2^2 / 2 >= 2 pad elements
+    nlive = jacobi_lds(C, X, len, rank, ldx, thr2, &sw, C.LO);
+  }
   ph_add(C, kPhJacobi, t0);
   if (C.tid == 0) {
     if (sw > C.sstat[1]) C.sstat[1] = sw;

@@ -139,6 +139,7 @@ struct GrapeArgs {
   c2* traj_dO;
   int mode;                // kModeForward | kModeBackward
   unsigned long long tag;  // fingerprint of the call's arguments
+  int jx_elems;            // global-scratch build: LDS for the Jacobi matrix (complex)
 };
 
 
@@ -161,6 +162,7 @@ struct EvolveArgs {
   size_t big_stride;
   int* flags;
   long long* stats;
+  int jx_elems;  // global-scratch build: LDS for the Jacobi matrix (complex)
 };
 
 
@@ -355,6 +357,18 @@ int threads_for_cap(int cap) {
 
 // Largest dynamic LDS a workgroup may use on gfx950.
 constexpr size_t kMaxDynLds = 160 * 1024 - sizeof(lds::Shared) - 512;
+// The global-scratch build can run the Jacobi of a bond update on an LDS
+// copy of its matrix (when rank x (pow2(len) + 1) + 2 pow2(len) complex fit):
+// LDS round trips instead of L2 ones, at the price of one workgroup per CU.
+// Measured at dcap 64 (N = 50, Heisenberg crosstalk): 21 % faster with one
+// trajectory per CU, 31 % with two (the co-resident workgroups of the
+// global-scratch Jacobi do not overlap), so it is the default at any count.
+// Mode -1 (default) and 1: on; 0: off.
+constexpr size_t kBigJacLds = (160 * 1024 - sizeof(big::Shared) - 512) / 16 * 16;
+std::atomic<int> g_jacobi_lds{-1};
+int jacobi_lds_elems() {
+  return g_jacobi_lds.load(std::memory_order_relaxed) == 0 ? 0 : (int)(kBigJacLds / sizeof(c2));
+}
 // Capacities up to kMaxLdsCap keep the working buffers in LDS; larger ones
 // (up to kMaxCap: a 2 cap x 2 cap bond problem of at most 256 columns for the
 // wave-level pivot search and sort) in per-trajectory global scratch.
@@ -436,6 +450,12 @@ int tnrg_plan_set_threads(int32_t dcap, int32_t threads) {
   return TNRG_OK;
 }
 
+int tnrg_plan_set_jacobi_lds(int32_t mode) {
+  if (mode < -1 || mode > 1) return fail(TNRG_EINVAL, "jacobi_lds mode = %d must be -1, 0 or 1", mode);
+  g_jacobi_lds.store(mode, std::memory_order_relaxed);
+  return TNRG_OK;
+}
+
 int32_t tnrg_plan_threads(int32_t dcap) {
   if (dcap < 1 || dcap > kMaxSites) return 0;
   return threads_for_cap(dcap);
@@ -507,14 +527,18 @@ int mps_evolve(const tnrg_model* md, const double* ux, const double* uy, const d
   A.l_end = l_end;
   A.adjoint = adjoint ? 1 : 0;
   launch_gates(md, ux, uy, gates, s);
+  A.jx_elems = in_lds ? 0 : jacobi_lds_elems();
   const void* kern = in_lds ? reinterpret_cast<const void*>(lds::k_evolve)
                             : reinterpret_cast<const void*>(big::k_evolve);
-  hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipError_t e = hipFuncSetAttribute(
+      kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+      (int)(in_lds ? lds : (size_t)A.jx_elems * sizeof(c2)));
   if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute(k_evolve)");
   if (in_lds)
     hipLaunchKernelGGL(lds::k_evolve, dim3(psi->n_traj), dim3(threads_for_cap(psi->dcap)), lds, s, A);
   else
-    hipLaunchKernelGGL(big::k_evolve, dim3(psi->n_traj), dim3(threads_for_cap(psi->dcap)), 0, s, A);
+    hipLaunchKernelGGL(big::k_evolve, dim3(psi->n_traj), dim3(threads_for_cap(psi->dcap)),
+                       (size_t)A.jx_elems * sizeof(c2), s, A);
   e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "k_evolve launch");
   return TNRG_OK;
@@ -686,7 +710,9 @@ int grape_launch(int mode, const tnrg_model* md, const double* ux, const double*
                                    : reinterpret_cast<const void*>(lds::k_grape<false>))
                             : (mid ? reinterpret_cast<const void*>(big::k_grape<true>)
                                    : reinterpret_cast<const void*>(big::k_grape<false>));
-  hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  A.jx_elems = in_lds ? 0 : jacobi_lds_elems();
+  const size_t dyn = in_lds ? lds : (size_t)A.jx_elems * sizeof(c2);
+  hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
   if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute(k_grape)");
   const dim3 grid(K * R), block(threads_for_cap(cap));
   if (in_lds && mid)
@@ -694,9 +720,9 @@ int grape_launch(int mode, const tnrg_model* md, const double* ux, const double*
   else if (in_lds)
     hipLaunchKernelGGL(lds::k_grape<false>, grid, block, lds, s, A);
   else if (mid)
-    hipLaunchKernelGGL(big::k_grape<true>, grid, block, 0, s, A);
+    hipLaunchKernelGGL(big::k_grape<true>, grid, block, dyn, s, A);
   else
-    hipLaunchKernelGGL(big::k_grape<false>, grid, block, 0, s, A);
+    hipLaunchKernelGGL(big::k_grape<false>, grid, block, dyn, s, A);
   e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "k_grape launch");
   const int MN = md->m * md->n;

@@ -122,6 +122,7 @@ _SIGS = {
     "tnrg_server_info_get": (ctypes.c_int, [_SP, ctypes.POINTER(_ServerInfo)]),
     "tnrg_server_destroy": (ctypes.c_int, [_SP]),
     "tnrg_plan_set_threads": (ctypes.c_int, [_i32, _i32]),
+    "tnrg_plan_set_jacobi_lds": (ctypes.c_int, [_i32]),
     "tnrg_plan_threads": (_i32, [_i32]),
     "tnrg_last_error": (ctypes.c_char_p, []),
     "tnrg_version": (ctypes.c_char_p, []),

@@ -187,6 +187,27 @@ def test_global_scratch_variant_is_bitwise_the_lds_variant(P):
         assert torch.equal(a[name], c[name]), name
 
 
+@pytest.mark.parametrize("dcap", [64, 128])
+def test_jacobi_in_lds_is_bitwise_the_global_one(P, dcap):
+    """Capacities above 32: the Jacobi on an LDS copy of its matrix and on
+    the global-scratch one give the same bits (ghz N = 12: bonds up to 64,
+    ranks above and below the LDS limit at dcap 128)."""
+    p = W.make_problem(task="ghz", N=12, M=8, T=5.0, chi=64, K=2, R=1, sigma=0.5, seed=31,
+                       amp=2.0)
+    say(f"jacobi in LDS vs global at dcap {dcap}")
+    lib = P.tnrg._lib
+    try:
+        assert lib.tnrg_plan_set_jacobi_lds(0) == 0
+        a = _grape_case(P, p, dcap=dcap)
+        assert lib.tnrg_plan_set_jacobi_lds(1) == 0
+        b = _grape_case(P, p, dcap=dcap)
+    finally:
+        lib.tnrg_plan_set_jacobi_lds(-1)
+    assert lib.tnrg_plan_set_jacobi_lds(2) != 0
+    for name in ("F", "g_ux", "g_uy", "g_uzz", "overlaps", "traj_dO"):
+        assert torch.equal(a[name], b[name]), name
+
+
 @pytest.mark.parametrize("N,M,T,chi", [(12, 10, 6.0, 64)])
 def test_large_bonds_match_oracle(P, N, M, T, chi):
     """Bond dimensions above 32 (63 and 64, the full rank of the middle bond):
