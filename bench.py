@@ -70,11 +70,14 @@ def cpu_baseline(name, n_traj, R, xt_model="zz"):
 
 
 def sources_sha256():
-    """Hash of the library sources, to match stored counter runs to this build."""
+    """Hash of the sources compiled into device code (the kernels, their
+    headers and the launching host file; not the host-only serving runtime),
+    to match stored counter runs to this build."""
     import glob
     import hashlib
     h = hashlib.sha256()
-    files = sorted(glob.glob(os.path.join(ROOT, "paper_2603_03639_amd", "csrc", "*")))
+    files = sorted(f for f in glob.glob(os.path.join(ROOT, "paper_2603_03639_amd", "csrc", "*"))
+                   if not f.endswith(".cpp"))
     for f in files + [os.path.join(ROOT, "include", "tnrg.h")]:
         with open(f, "rb") as fh:
             h.update(fh.read())

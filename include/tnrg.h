@@ -327,7 +327,9 @@ int tnrg_server_create(void *arena, size_t arena_bytes, int32_t n_streams,
                        int32_t max_bypass, int32_t max_dcap,
                        tnrg_server **out);
 /* Validates and queues a request; *ticket identifies its completion.  Does
- * not launch: tnrg_server_progress does. */
+ * not launch: tnrg_server_progress does.  Without a fixed req->dcap the
+ * capacity buckets tried start at the larger of the input and target batch
+ * capacities (the states hold those MPS before their first truncation). */
 int tnrg_server_submit(tnrg_server *s, const tnrg_request *req,
                        int64_t *ticket);
 /* Non-blocking step of the loop: collects finished launches (regrowing

@@ -10,6 +10,7 @@
 // device arena, so admission is by HBM footprint.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cstdarg>
 #include <cstdio>
@@ -142,13 +143,16 @@ void plan_put(const PlanKey& k, int cap) {
 
 // Buckets to try: 4, 8, ... below min(chi, 2^(N/2)), then that value, all
 // at most max_dcap, starting from the plan's bucket `start` when there is one.
-std::vector<int> bucket_sequence(const tnrg_model& md, int start, int max_dcap) {
+// floor: no bucket below the capacity of the request's input and target
+// batches (the states hold them before their first truncation to chi).
+std::vector<int> bucket_sequence(const tnrg_model& md, int start, int max_dcap, int floor) {
   const int half = md.n / 2;
   int cap_max = md.chi;
   if (half < 30 && (1 << half) < cap_max) cap_max = 1 << half;
+  if (cap_max < floor) cap_max = floor;
   std::vector<int> seq;
   for (int b : {4, 8, 16, 32, 64, 128})
-    if (b < cap_max && b <= max_dcap) seq.push_back(b);
+    if (b >= floor && b < cap_max && b <= max_dcap) seq.push_back(b);
   if (cap_max <= max_dcap) seq.push_back(cap_max);
   if (seq.empty()) seq.push_back(max_dcap < cap_max ? max_dcap : cap_max);
   if (start > 0) {
@@ -371,7 +375,7 @@ int tnrg_server_submit(tnrg_server* s, const tnrg_request* req, int64_t* ticket)
     job->buckets = {req->dcap};
   } else {
     job->buckets = bucket_sequence(job->model, plan_get(PlanKey(md->n, md->m, md->chi, md->xt_model, req->K, req->R)),
-                                   s->max_dcap);
+                                   s->max_dcap, std::max(job->in.dcap, job->tg.dcap));
   }
   job->ticket = s->next_ticket++;
   job->t_submit = Clock::now();

@@ -222,6 +222,15 @@ class MPSBatch:
             (n_traj, self.elems), dtype=torch.complex128, device=device)
         self.dims = dims if dims is not None else torch.ones(
             (n_traj, N + 1), dtype=torch.int32, device=device)
+        self._max_dim = None if dims is not None else 1
+
+    @property
+    def max_dim(self) -> int:
+        """Largest bond dimension in the batch (read from the device once
+        unless the batch was built from host tensors)."""
+        if self._max_dim is None:
+            self._max_dim = int(self.dims.max())
+        return self._max_dim
 
     def c(self) -> _Batch:
         return _Batch(self.n_traj, self.N, self.dcap, self.dims.data_ptr(),
@@ -250,8 +259,10 @@ class MPSBatch:
                 host[t, o:o + Dl * 2 * cr] = blk.reshape(-1)
                 dims[t, j] = Dl
                 dims[t, j + 1] = Dr
-        return cls(N, len(states), dcap, device,
-                   torch.from_numpy(host).to(device), torch.from_numpy(dims).to(device))
+        out = cls(N, len(states), dcap, device,
+                  torch.from_numpy(host).to(device), torch.from_numpy(dims).to(device))
+        out._max_dim = int(dims.max())
+        return out
 
     @classmethod
     def from_product(cls, vecs, device="cuda") -> "MPSBatch":
@@ -344,9 +355,12 @@ BUCKETS = (4, 8, 16, 32, 64, 128)
 _plan_cache = {}
 
 
-def _bucket_sequence(model: Model, start: Optional[int]):
-    cap_max = min(model.chi, 2 ** min(model.N // 2, 30))
-    seq = [b for b in BUCKETS if b < cap_max] + [cap_max]
+def _bucket_sequence(model: Model, start: Optional[int], floor: int = 1):
+    """Capacities to try: the buckets up to min(chi, 2^(N/2)), none below
+    ``floor`` (the largest bond of the inputs and targets, which the states
+    must hold before their first truncation to chi)."""
+    cap_max = max(min(model.chi, 2 ** min(model.N // 2, 30)), floor)
+    seq = [b for b in BUCKETS if floor <= b < cap_max] + [cap_max]
     if start is not None:
         seq = [b for b in seq if b >= start] or [cap_max]
     return seq
@@ -425,7 +439,8 @@ def prepare(model: Model, ux, uy, uzz, J, inputs: MPSBatch, targets: MPSBatch,
     model.check_J(J, K)
     key = (model.N, model.M, model.chi, model.xt_model, K, R)
     start = dcap if dcap is not None else _plan_cache.get(key)
-    seq = [dcap] if dcap is not None else _bucket_sequence(model, start)
+    floor = max(inputs.max_dim, targets.max_dim)
+    seq = [dcap] if dcap is not None else _bucket_sequence(model, start, floor)
     last = None
     for cap in seq:
         call = GrapeCall(model, K, R, inputs, targets, cap, ckpt_stride, want_traj_dO, dev)
@@ -466,7 +481,8 @@ def grape_fidelity_grad(model: Model, ux, uy, uzz, J, inputs: MPSBatch, targets:
     model.check_J(J, K)
     key = (model.N, model.M, model.chi, model.xt_model, K, R)
     start = dcap if dcap is not None else _plan_cache.get(key)
-    seq = [dcap] if dcap is not None else _bucket_sequence(model, start)
+    floor = max(inputs.max_dim, targets.max_dim)
+    seq = [dcap] if dcap is not None else _bucket_sequence(model, start, floor)
     last = None
     for cap in seq:
         call = GrapeCall(model, K, R, inputs, targets, cap, ckpt_stride, want_traj_dO, dev)

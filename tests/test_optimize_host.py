@@ -56,3 +56,16 @@ def test_parasitic_count(O):
     # Heisenberg: three strengths on each of the 9 bonds
     assert O.parasitic_count(tnrg.Model.from_problem(pz)) == 4
     assert O.parasitic_count(tnrg.Model.from_problem(ph)) == 27
+
+
+def test_bucket_sequence_floor(O):
+    """The capacity search never tries a bucket below the largest bond of the
+    inputs and targets, even where chi is smaller (the states hold them
+    before their first truncation to chi)."""
+    from paper_2603_03639_amd import tnrg
+    m = lambda N, chi: tnrg.Model(N=N, M=1, dt=0.1, chi=chi)
+    assert tnrg._bucket_sequence(m(50, 64), None) == [4, 8, 16, 32, 64]
+    assert tnrg._bucket_sequence(m(50, 64), None, floor=5) == [8, 16, 32, 64]
+    assert tnrg._bucket_sequence(m(8, 1), None) == [1]
+    assert tnrg._bucket_sequence(m(8, 1), None, floor=2) == [2]
+    assert tnrg._bucket_sequence(m(50, 64), 16, floor=2) == [16, 32, 64]
