@@ -246,7 +246,8 @@ int tnrg_status(const void *ws, int32_t n_traj, int32_t *host_flags,
 /*
  * Launch plan (process-wide): the workgroup size used for internal states of
  * capacity dcap, one of 64, 128 or 256 threads (1, 2 or 4 waves per
- * trajectory); 0 restores the built-in choice.  Results do not depend on it
+ * trajectory), or 512 for capacities above 32 (TNRG_EINVAL otherwise); 0
+ * restores the built-in choice.  Results do not depend on it
  * beyond rounding.  The autotuner of the Python binding times the choices on
  * the caller's workload and stores the fastest here.
  */

@@ -444,8 +444,10 @@ extern "C" {
 
 int tnrg_plan_set_threads(int32_t dcap, int32_t threads) {
   if (dcap < 1 || dcap > kMaxSites) return fail(TNRG_EINVAL, "dcap = %d out of range", dcap);
-  if (threads != 0 && threads != 64 && threads != 128 && threads != 256)
-    return fail(TNRG_EINVAL, "threads = %d must be 0, 64, 128 or 256", threads);
+  if (threads != 0 && threads != 64 && threads != 128 && threads != 256 && threads != 512)
+    return fail(TNRG_EINVAL, "threads = %d must be 0, 64, 128, 256 or 512", threads);
+  if (threads == 512 && use_lds(dcap))
+    return fail(TNRG_EINVAL, "512 threads only for capacities above %d", kMaxLdsCap);
   g_plan_threads[dcap].store(threads, std::memory_order_relaxed);
   return TNRG_OK;
 }

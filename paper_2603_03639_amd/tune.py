@@ -19,6 +19,8 @@ import torch
 from . import tnrg
 
 CANDIDATES = (64, 128, 256)
+# capacities above 32 (global-scratch build) may also run 512 threads
+BIG_CANDIDATES = (64, 128, 256, 512)
 _tuned: Dict[tuple, int] = {}
 
 
@@ -32,8 +34,11 @@ def threads(dcap: int) -> int:
 
 def autotune(model: "tnrg.Model", ux, uy, uzz, J, inputs: "tnrg.MPSBatch",
              targets: "tnrg.MPSBatch", dcap: int, slices: int = 16,
-             candidates: Sequence[int] = CANDIDATES, repeats: int = 1) -> dict:
-    """Pick the fastest workgroup size for ``dcap`` on a prefix of the problem."""
+             candidates: Sequence[int] = None, repeats: int = 1) -> dict:
+    """Pick the fastest workgroup size for ``dcap`` on a prefix of the problem
+    (the candidates default to CANDIDATES, BIG_CANDIDATES above capacity 32)."""
+    if candidates is None:
+        candidates = BIG_CANDIDATES if dcap > 32 else CANDIDATES
     K, R = int(J.shape[0]), inputs.n_traj
     key = (model.N, dcap, K * R, model.chi)
     if key in _tuned:

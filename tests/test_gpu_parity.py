@@ -208,16 +208,23 @@ def test_jacobi_in_lds_is_bitwise_the_global_one(P, dcap):
         assert torch.equal(a[name], b[name]), name
 
 
-@pytest.mark.parametrize("N,M,T,chi", [(12, 10, 6.0, 64)])
-def test_large_bonds_match_oracle(P, N, M, T, chi):
+@pytest.mark.parametrize("N,M,T,chi,threads", [(12, 10, 6.0, 64, 0), (12, 10, 6.0, 64, 512)])
+def test_large_bonds_match_oracle(P, N, M, T, chi, threads):
     """Bond dimensions above 32 (63 and 64, the full rank of the middle bond):
-    the global-scratch variant against the oracle."""
+    the global-scratch variant against the oracle, with the default
+    workgroup and with 512 threads."""
     p = W.make_problem(task="ghz", N=N, M=M, T=T, chi=chi, K=2, R=1, sigma=0.5, seed=31,
                        amp=2.0)
-    say(f"large bonds: ghz N={N} M={M} chi={chi}")
+    say(f"large bonds: ghz N={N} M={M} chi={chi} threads={threads}")
     for k in range(p.K):
         assert min(cut_gaps(p, k, 0)) >= 1e-8
-    res = _grape_case(P, p)
+    lib = P.tnrg._lib
+    try:
+        assert lib.tnrg_plan_set_threads(64, threads) == 0
+        res = _grape_case(P, p)
+    finally:
+        lib.tnrg_plan_set_threads(64, 0)
+    assert lib.tnrg_plan_set_threads(16, 512) != 0
     assert res["dcap"] > 32 and res["info"]["max_dim"] > 32
     ref = og.fidelity_grad(p, details=True)
     F = float(res["F"].cpu())
