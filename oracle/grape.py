@@ -55,24 +55,26 @@ def environments(bra: MPS, ket: MPS):
     N = len(ket)
     E = [None] * (N + 1)
     F = [None] * (N + 1)
+    d = ket[0].shape[1]
     E[0] = np.ones((1, 1), np.complex128)
     for j in range(N):
         E[j + 1] = sum(bra[j][:, s, :].conj().T @ E[j] @ ket[j][:, s, :]
-                       for s in range(2))
+                       for s in range(d))
     F[N] = np.ones((1, 1), np.complex128)
     for j in range(N - 1, -1, -1):
         F[j] = sum(ket[j][:, s, :] @ F[j + 1] @ bra[j][:, s, :].conj().T
-                   for s in range(2))
+                   for s in range(d))
     return E, F
 
 
 def transitions(bra: MPS, ket: MPS, E, F) -> np.ndarray:
-    """rho[j, s, s'] = <bra| (|s><s'|)_j |ket>, shape (N, 2, 2)."""
+    """rho[j, s, s'] = <bra| (|s><s'|)_j |ket>, shape (N, d, d)."""
     N = len(ket)
-    rho = np.zeros((N, 2, 2), np.complex128)
+    d = ket[0].shape[1]
+    rho = np.zeros((N, d, d), np.complex128)
     for j in range(N):
-        for s in range(2):
-            for t in range(2):
+        for s in range(d):
+            for t in range(d):
                 rho[j, s, t] = np.trace(bra[j][:, s, :].conj().T @ E[j]
                                         @ ket[j][:, t, :] @ F[j + 1])
     return rho
@@ -82,13 +84,14 @@ def two_site_element(bra: MPS, ket: MPS, E, F, b: int, G1: np.ndarray,
                      G2: np.ndarray) -> complex:
     """<bra| (G1)_b (G2)_{b+1} |ket>."""
     val = 0.0 + 0.0j
-    for s1 in range(2):
-        for t1 in range(2):
+    d = ket[0].shape[1]
+    for s1 in range(d):
+        for t1 in range(d):
             if G1[s1, t1] == 0:
                 continue
             W = bra[b][:, s1, :].conj().T @ E[b] @ ket[b][:, t1, :]
-            for s2 in range(2):
-                for t2 in range(2):
+            for s2 in range(d):
+                for t2 in range(d):
                     if G2[s2, t2] == 0:
                         continue
                     val += G1[s1, t1] * G2[s2, t2] * np.trace(

@@ -1,6 +1,6 @@
 """Matrix-product states (oracle; test infrastructure only).
 
-An MPS is a list of N complex128 arrays A[j] of shape (D_j, 2, D_{j+1}) with
+An MPS is a list of N complex128 arrays A[j] of shape (D_j, d, D_{j+1}) with
 D_0 = D_N = 1, the state being
     psi(s_0 .. s_{N-1}) = A[0][:, s_0, :] A[1][:, s_1, :] ... A[N-1][:, s_{N-1}, :]
 (the first and last factors are row and column vectors, Sec. II).
@@ -34,7 +34,7 @@ def overlap(bra: MPS, ket: MPS) -> complex:
     """
     E = np.ones((1, 1), np.complex128)
     for B, A in zip(bra, ket):
-        E = sum(B[:, s, :].conj().T @ E @ A[:, s, :] for s in range(2))
+        E = sum(B[:, s, :].conj().T @ E @ A[:, s, :] for s in range(A.shape[1]))
     return complex(E[0, 0])
 
 
@@ -46,8 +46,8 @@ def to_dense(mps: MPS) -> np.ndarray:
     """State vector, site 0 being the most significant qubit."""
     v = np.ones((1, 1), np.complex128)  # (amplitude index, right bond)
     for A in mps:
-        Dl, _, Dr = A.shape
-        v = (v @ A.reshape(Dl, 2 * Dr)).reshape(-1, Dr)
+        Dl, d, Dr = A.shape
+        v = (v @ A.reshape(Dl, d * Dr)).reshape(-1, Dr)
     return v[:, 0].copy()
 
 
@@ -57,11 +57,11 @@ def right_canonicalize(mps: MPS) -> MPS:
     out = copy(mps)
     for j in range(len(out) - 1, 0, -1):
         A = out[j]
-        Dl, _, Dr = A.shape
+        Dl, d, Dr = A.shape
         # A = L Q with orthonormal rows of Q: QR of A^dagger.
-        q, r = np.linalg.qr(A.reshape(Dl, 2 * Dr).conj().T)
+        q, r = np.linalg.qr(A.reshape(Dl, d * Dr).conj().T)
         k = q.shape[1]
-        out[j] = q.conj().T.reshape(k, 2, Dr)
+        out[j] = q.conj().T.reshape(k, d, Dr)
         L = r.conj().T                      # (Dl, k)
         P = out[j - 1]
         out[j - 1] = np.einsum("asb,bc->asc", P, L)

@@ -57,13 +57,14 @@ def _svd(m: np.ndarray):
 
 def split_two_site(theta: np.ndarray, chi: int, eps: float, renormalize: bool,
                    left_to_right: bool, stats: Optional[List[Dict]] = None):
-    """Split theta (Dl, 2, 2, Dr) into (Dl, 2, k) and (k, 2, Dr).
+    """Split theta (Dl, d, d, Dr) into (Dl, d, k) and (k, d, Dr) (d = 2 for
+    qubit states, 4 for the operators of oracle/mpo.py).
 
     Left to right: left factor U (left-isometric), right factor diag(s) V^dagger
     (new centre).  Right to left: left factor U diag(s), right V^dagger.
     """
-    Dl, _, _, Dr = theta.shape
-    U, S, Vh = _svd(theta.reshape(Dl * 2, 2 * Dr))
+    Dl, d, _, Dr = theta.shape
+    U, S, Vh = _svd(theta.reshape(Dl * d, d * Dr))
     k = keep_count(S, chi, eps)
     k = min(k, S.size)
     s = S[:k].copy()
@@ -84,7 +85,7 @@ def split_two_site(theta: np.ndarray, chi: int, eps: float, renormalize: bool,
     else:
         left = U[:, :k] * s[None, :]
         right = Vh[:k, :]
-    return left.reshape(Dl, 2, k), right.reshape(k, 2, Dr)
+    return left.reshape(Dl, d, k), right.reshape(k, d, Dr)
 
 
 def bond_sweep(mps: MPS, gate, left_to_right: bool, chi: int, eps: float,
