@@ -271,7 +271,11 @@ def main():
     import numpy as np
     import torch
 
-    from paper_2603_03639_amd import build as B
+    import importlib.util
+    spec = importlib.util.spec_from_file_location(
+        "_tnrg_build", os.path.join(ROOT, "paper_2603_03639_amd", "build.py"))
+    B = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(B)
     if not os.path.exists(B.LIB_PATH):
         B.build()
     import paper_2603_03639_amd as P

@@ -14,10 +14,8 @@ HEADER = os.path.join(ROOT, "include", "tnrg.h")
 
 @pytest.fixture(scope="module")
 def lib():
-    from paper_2603_03639_amd import build as B
-    if not os.path.exists(B.LIB_PATH):
-        B.build()
-    return ctypes.CDLL(B.LIB_PATH)
+    from conftest import ensure_library
+    return ctypes.CDLL(ensure_library())
 
 
 def declared_functions():

@@ -13,9 +13,8 @@ import workloads as W
 
 @pytest.fixture(scope="module")
 def O():
-    from paper_2603_03639_amd import build as B
-    if not os.path.exists(B.LIB_PATH):
-        B.build()
+    from conftest import ensure_library
+    ensure_library()
     from paper_2603_03639_amd import optimize
     return optimize
 
