@@ -259,6 +259,8 @@ def main():
                          "J^x XX + J^y YY + J^z ZZ, uniform in [-0.05, 0.05], on every bond")
     ap.add_argument("--K", type=int, default=0,
                     help="noise samples: the first K of the workload's (0: all of them)")
+    ap.add_argument("--threads", type=int, default=None,
+                    help="threads per trajectory (workgroup size) instead of the autotuner's choice")
     ap.add_argument("--plain", type=int, default=8,
                     help="trajectories run one at a time for the plain GPU path (0 disables)")
     args = ap.parse_args()
@@ -305,7 +307,11 @@ def main():
     log(f"plan: dcap={plan['dcap']} max_dim={plan['info']['max_dim']} "
         f"({time.perf_counter() - t0:.2f} s incl. bucket search)")
     from paper_2603_03639_amd import tune
-    tuned = tune.autotune(model, ux, uy, uzz, J, inputs, targets, plan["dcap"])
+    if args.threads is None:
+        tuned = tune.autotune(model, ux, uy, uzz, J, inputs, targets, plan["dcap"])
+    else:
+        tune.set_threads(plan["dcap"], args.threads)
+        tuned = {"threads": args.threads, "forced": True}
     log(f"autotune: {tuned}")
     # checkpoint stride: keep as many forward states as 60% of the free HBM
     # holds (stride 1 recomputes nothing); --ckpt-stride forces one

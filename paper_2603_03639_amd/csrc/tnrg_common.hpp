@@ -57,6 +57,61 @@ __device__ __forceinline__ c2 cfmac(c2 a, c2 b, c2 acc) {
 }
 __device__ __forceinline__ double cabs2(c2 a) { return fma(a.x, a.x, a.y * a.y); }
 
+// ----------------------------------------------------------------------------
+// Complex matrix product on the fp64 matrix cores:
+//   out(i, j) = sum_q a(i, q) b(q, j),   i < m, j < n, q < kd
+// in 16 x 16 output tiles, one tile per wave at a time (tile t on wave
+// t mod waves), q in steps of 4 through v_mfma_f64_16x16x4f64.  The complex
+// product takes three real products per step (Gauss): P1 = ar br,
+// P2 = ai bi, P3 = (ar + ai)(br + bi); re = P1 - P2, im = P3 - P1 - P2.
+// The operands of kSteps steps are loaded before their products are
+// issued, so a tile waits for memory once per 4 kSteps of depth.  Operand layout of
+// the instruction: lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16] of
+// the 16 x 4 and 4 x 16 blocks; item v of lane l holds C[4 v + l / 16][l % 16].
+// Out-of-range operands are read as zero (fa, fb are only called in range),
+// fs(i, j, value) is called once per output element in range.  The summation
+// order of an element depends only on kd, never on the thread count.  Every
+// thread of the workgroup calls it (nt a multiple of 64); no barrier inside.
+typedef double v4d __attribute__((ext_vector_type(4)));
+template <int kSteps, class FA, class FB, class FS>
+__device__ __forceinline__ void cgemm_mfma(int tid, int nt, int m, int n, int kd, FA fa, FB fb,
+                                           FS fs) {
+  const int lane = tid & 63;
+  const int li = lane & 15, lq = lane >> 4;
+  const int tn = (n + 15) >> 4;
+  const int ntile = ((m + 15) >> 4) * tn;
+  for (int t = tid >> 6; t < ntile; t += nt >> 6) {
+    const int i0 = (t / tn) << 4, j0 = (t % tn) << 4;
+    const int ia = i0 + li, jb = j0 + li;
+    const bool arow = ia < m, bcol = jb < n;
+    v4d p1 = {0.0, 0.0, 0.0, 0.0}, p2 = {0.0, 0.0, 0.0, 0.0}, p3 = {0.0, 0.0, 0.0, 0.0};
+    for (int q0 = 0; q0 < kd; q0 += 4 * kSteps) {
+      c2 a[kSteps], b[kSteps];
+#pragma unroll
+      for (int u = 0; u < kSteps; ++u) {
+        const int q = q0 + 4 * u + lq;
+        a[u] = (arow && q < kd) ? fa(ia, q) : cmk(0.0, 0.0);
+        b[u] = (q < kd && bcol) ? fb(q, jb) : cmk(0.0, 0.0);
+      }
+#pragma unroll
+      for (int u = 0; u < kSteps; ++u) {
+        if (q0 + 4 * u < kd) {  // uniform across the wave
+          p1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u].x, b[u].x, p1, 0, 0, 0);
+          p2 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u].y, b[u].y, p2, 0, 0, 0);
+          p3 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u].x + a[u].y, b[u].x + b[u].y, p3, 0, 0, 0);
+        }
+      }
+    }
+    if (bcol) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = i0 + 4 * v + lq;
+        if (i < m) fs(i, jb, cmk(p1[v] - p2[v], p3[v] - p1[v] - p2[v]));
+      }
+    }
+  }
+}
+
 // 2x2 complex matrix, row-major g[s][t] = m[2*s+t]
 struct M22 {
   c2 m[4];

@@ -36,6 +36,11 @@ typedef TNRG_AS long long sll;
 // columns (four values per lane), groups of up to 64 lanes and rounds with
 // more pairs than lane groups.
 constexpr bool kWide = TNRG_BIG;
+// Depth steps of 4 whose operands a matrix-core product tile loads at once:
+// 4 in the global-scratch build, whose operands come from L2 and whose depths
+// reach 256; 1 in the LDS build, whose depths of at most 64 (mostly 16) come
+// from LDS (measured at bond dimension 16: batching 8 steps cost 1 % there).
+constexpr int kMfmaSteps = TNRG_BIG ? 4 : 1;
 constexpr int kLaneQuads = TNRG_BIG ? 4 : 1;
 __device__ __forceinline__ double gsum(double v, int G) {
   double red[1] = {v};
@@ -783,18 +788,17 @@ __device__ __forceinline__ int bond_split(Ctx& C, const sc2* Lt, const sc2* Rt, 
   for (int idx = C.tid; idx < nc * ldx; idx += C.nt) X[idx] = X0[idx];
   __syncthreads();
   // Dm[i][c] = sum_r conj(Q_i[r]) theta_c[r]  -> new centre in LC
-  for (DivWalk w(C.tid, C.nt, nc); w.idx < k * nc; w.next()) {
-    const int i = w.q;
-    const int c = w.r;
-    const sc2* qi = Q + i * len;
-    const sc2* xc = X + c * ldx;
-    c2 acc = cmk(0.0, 0.0);
-#pragma unroll 4
-    for (int r = 0; r < len; ++r) acc = cfmac(qi[r], xc[r], acc);
-    if (ltr)
-      C.LC[i * nc + c] = cscale(acc, inv);
-    else
-      C.LC[c * k + i] = cscale(cconj(acc), inv);
+  {
+    sc2* LC = C.LC;
+    cgemm_mfma<kMfmaSteps>(C.tid, C.nt, k, nc, len,
+               [&](int i, int r) { return cconj(Q[i * len + r]); },
+               [&](int r, int c) { return X[c * ldx + r]; },
+               [&](int i, int c, c2 acc) {
+                 if (ltr)
+                   LC[i * nc + c] = cscale(acc, inv);
+                 else
+                   LC[c * k + i] = cscale(cconj(acc), inv);
+               });
   }
   // isometry to HBM with the finishing gate
   if (!iso) {
@@ -1233,26 +1237,36 @@ __device__ __forceinline__ c2 left_envs(Ctx& C, const c2* bra, const int* bd, co
     const c2* Bt = bra + Lb.off[j];
     const int bcap = Lb.cap[j + 1];
     if (C.tid == 0) C.sstat[5] += 16LL * (bl * ar * al + br * ar * bl);
-    // T[s][z][y] = sum_w E[z][w] A[w,s,y]   (bl x ar)
-    for (DivWalk w(C.tid, C.nt, ar); w.idx < 2 * bl * ar; w.next()) {
-      const int s = w.q >= bl ? 1 : 0;
-      const int z = w.q - s * bl, y = w.r;
-      c2 acc = cmk(0.0, 0.0);
-#pragma unroll 4
-      for (int w = 0; w < al; ++w) acc = cfma(eb.E[z * al + w], A[(size_t)(w * 2 + s) * acap + y], acc);
-      eb.TF[s * cc + z * ar + y] = acc;
+    // T[s][z][y] = sum_w E[z][w] A[w,s,y]: bl x (2 ar), column (s, y)
+    {
+      sc2* E = eb.E;
+      sc2* TF = eb.TF;
+      cgemm_mfma<kMfmaSteps>(C.tid, C.nt, bl, 2 * ar, al,
+                 [&](int z, int w) { return E[z * al + w]; },
+                 [&](int w, int c) {
+                   const int s = c >= ar ? 1 : 0;
+                   return A[(size_t)(w * 2 + s) * acap + c - s * ar];
+                 },
+                 [&](int z, int c, c2 v) {
+                   const int s = c >= ar ? 1 : 0;
+                   TF[s * cc + z * ar + c - s * ar] = v;
+                 });
     }
     __syncthreads();
-    // E'[x][y] = sum_s sum_z conj(B[z,s,x]) T[s][z][y]   (br x ar)
-    for (DivWalk w(C.tid, C.nt, ar); w.idx < br * ar; w.next()) {
-      const int x = w.q, y = w.r;
-      const int idx = w.idx;
-      c2 acc = cmk(0.0, 0.0);
-      for (int s = 0; s < 2; ++s)
-#pragma unroll 4
-        for (int z = 0; z < bl; ++z)
-          acc = cfmac(Bt[(size_t)(z * 2 + s) * bcap + x], eb.TF[s * cc + z * ar + y], acc);
-      eb.E[idx] = acc;
+    // E'[x][y] = sum_{s,z} conj(B[z,s,x]) T[s][z][y]: br x ar, depth (s, z)
+    {
+      sc2* E = eb.E;
+      sc2* TF = eb.TF;
+      cgemm_mfma<kMfmaSteps>(C.tid, C.nt, br, ar, 2 * bl,
+                 [&](int x, int q) {
+                   const int s = q >= bl ? 1 : 0;
+                   return cconj(Bt[(size_t)((q - s * bl) * 2 + s) * bcap + x]);
+                 },
+                 [&](int q, int y) {
+                   const int s = q >= bl ? 1 : 0;
+                   return TF[s * cc + (q - s * bl) * ar + y];
+                 },
+                 [&](int x, int y, c2 v) { E[x * ar + y] = v; });
     }
     __syncthreads();
   }
