@@ -5,7 +5,8 @@ The persistent kernel runs one workgroup per trajectory.  With few
 trajectories per SIMD the bond update is latency-bound, and 2 or 4 waves per
 trajectory can hide latency better than one; which is fastest depends on the
 bond dimensions the workload reaches.  ``autotune`` times each candidate on a
-short prefix of the caller's own problem (same N, capacity, ensemble size) and
+prefix of the caller's own problem (same N, capacity, ensemble size; long
+enough for its bonds to reach half the capacity, within half the slices) and
 stores the winner in the library's process-wide plan (tnrg_plan_set_threads).
 Results do not depend on the choice beyond rounding.
 """
@@ -44,10 +45,22 @@ def autotune(model: "tnrg.Model", ux, uy, uzz, J, inputs: "tnrg.MPSBatch",
     if key in _tuned:
         set_threads(dcap, _tuned[key])
         return {"threads": _tuned[key], "cached": True}
-    Ms = max(1, min(model.M, slices))
     import dataclasses
-    sub = dataclasses.replace(model, M=Ms)
-    args = [a[:Ms].contiguous() for a in (ux, uy, uzz)] + [J]
+    Ms = max(1, min(model.M, slices))
+    # A prefix whose bonds stay far below the bucket times the small-bond
+    # regime, where fewer threads win; lengthen it (doubling, up to half of
+    # the slices) until its largest bond reaches half the capacity.
+    while True:
+        sub = dataclasses.replace(model, M=Ms)
+        args = [a[:Ms].contiguous() for a in (ux, uy, uzz)] + [J]
+        call = tnrg.GrapeCall(sub, K, R, inputs, targets, dcap, device=inputs.data.device)
+        call.run(*args)
+        torch.cuda.synchronize()
+        reached = call.check()["max_dim"]
+        del call
+        if 2 * reached >= dcap or 2 * Ms > max(slices, model.M // 2):
+            break
+        Ms *= 2
     times = {}
     for nt in candidates:
         set_threads(dcap, nt)
@@ -66,7 +79,8 @@ def autotune(model: "tnrg.Model", ux, uy, uzz, J, inputs: "tnrg.MPSBatch",
     win = min(times, key=times.get)
     set_threads(dcap, win)
     _tuned[key] = win
-    return {"threads": win, "cached": False, "seconds": times, "slices": Ms}
+    return {"threads": win, "cached": False, "seconds": times, "slices": Ms,
+            "prefix_max_dim": reached}
 
 
 def ckpt_stride(model: "tnrg.Model", K: int, R: int, dcap: int, budget_bytes=None,
