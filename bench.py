@@ -72,7 +72,7 @@ def cpu_baseline(name, n_traj, R, xt_model="zz"):
 def sources_sha256():
     """Hash of the sources compiled into device code (the kernels, their
     headers and the launching host file; not the host-only serving runtime),
-    to match stored counter runs to this build."""
+    to match stored counter runs to the compiled library."""
     import glob
     import hashlib
     h = hashlib.sha256()
@@ -266,7 +266,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the trajectory batch "
-              "would be split across GPUs with one all-reduce of [F, grad], which this build "
+              "would be split across GPUs with one all-reduce of [F, grad], which this library "
               "does not implement.", file=sys.stderr)
         sys.exit(2)
 
