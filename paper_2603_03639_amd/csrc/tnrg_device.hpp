@@ -696,6 +696,27 @@ __device__ __forceinline__ int bond_split(Ctx& C, const sc2* Lt, const sc2* Rt, 
   // couples (s,s') only with (1-s,1-s'): one item makes the pair
   // (0,s') / (1,1-s') of row pair a and column c
   const int npair = 2 * dl * dr;
+  if (!offd && dm > 32) {
+    // large inner bond (global-scratch build only, so both builds agree
+    // bitwise on every problem they share): theta on the matrix cores, the
+    // diagonal bond gate (phase index s xor s') applied as each element is
+    // stored
+    cgemm_mfma<kMfmaSteps>(
+        C.tid, C.nt, 2 * dl, 2 * dr, dm,
+        [&](int r, int b) { return Lt[r * dm + b]; },
+        [&](int b, int col) { return Rt[b * 2 * dr + col]; },
+        [&](int r, int col, c2 t) {
+          const int sx = (r & 1) ^ (col >= dr ? 1 : 0);
+          const c2 v = cmul(t, sx ? bg.d[1] : bg.d[0]);
+          if (ltr) {
+            X[col * ldx + r] = v;
+            X0[col * ldx + r] = v;
+          } else {
+            X[r * ldx + col] = cconj(v);
+            X0[r * ldx + col] = cconj(v);
+          }
+        });
+  } else
   for (DivWalk w(C.tid, C.nt, 2 * dr); w.idx < npair; w.next()) {
     const int a = w.q;
     const int col0 = w.r;
